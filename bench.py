@@ -1,0 +1,243 @@
+"""Throughput of the SNeRG render path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs plain,batched,adjoint]
+
+Headline (value): forward Mrays/s of the plain FP32 path on the 512^3 grid
+(B = 32, ~10.6% occupied procedural shell) for one 800x800 camera, with
+inputs resident in device memory; fps = value / 0.64.  Further legs, each
+timed the same way: the batched FP16-MFMA-MLP forward (1024^3 grid, 16
+cameras of mixed size in one persistent launch replayed from a HIP graph)
+with its max-abs error against the FP64 oracle, and the adjoint (8 views at
+800x800 on a float32 shadow of the 512^3 grid, forward + backward).
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def time_launches(fn, steps, warmup, torch):
+    """Runs fn warmup times, then times `steps` calls with events on the
+    current stream (the stream the library launches on).  Returns ms/call."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def frame_counters(S, h, dg, cams):
+    """Exact per-ray counters of the march (GPU trace, bit-identical to the oracle's)."""
+    import torch
+    _, _, ctr = S.trace_visits(h, dg, cams, opts=S.make_opts(mlp_on=False), max_visits=0)
+    torch.cuda.synchronize()
+    c = ctr.cpu().numpy().astype(np.int64)
+    return dict(blocks=int(c[:, 0].sum()), occupied=int(c[:, 1].sum()), inblock=int(c[:, 2].sum()),
+                active=int(c[:, 3].sum()), rays=int(c.shape[0]))
+
+
+def algorithmic_bytes(cnt):
+    """The method's own traffic per the paper's accounting (Appendix A): one
+    indirection entry per macroblock traversed (4 B), one density byte per
+    in-block sample, 8 corners x 8 B per composited sample, 16 B of RGBA."""
+    return 4 * cnt["blocks"] + cnt["inblock"] + 64 * cnt["active"] + 16 * cnt["rays"]
+
+
+def leg_plain(args, torch, S, W, O):
+    cfg = W.config("plain512")
+    g, cams, mlp = cfg["grid"], cfg["cams"], cfg["mlp"]
+    h = S.Handle()
+    dg = S.DeviceGrid(h, g.N, g.B, g.indirection, g.dens, g.rgb, g.feat)
+    m = S.mlp_tensor(mlp)
+    n = sum(c.n_rays for c in cams)
+    out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    carr = S.make_cameras(cams)
+    opts = S.make_opts()
+    grid = dg.struct()
+
+    def step():
+        S.snerg_render(h, grid, m, carr, None, n, opts, out)
+
+    log(f"plain512: {g.n_blocks} blocks ({g.meta['occupancy']:.3f}), {n} rays; warmup {args.warmup}, steps {args.steps}")
+    ms = time_launches(step, args.steps, args.warmup, torch)
+    cnt = frame_counters(S, h, dg, cams)
+    abytes = algorithmic_bytes(cnt)
+    res = dict(ms=ms, rays=n, mrays=n / ms / 1e3, counters=cnt, alg_bytes=abytes, out=out, cams=cams, g=g, mlp=mlp)
+    log(f"plain512: {ms:.3f} ms/frame, {res['mrays']:.1f} Mrays/s, {abytes / ms / 1e6:.1f} GB/s algorithmic")
+    return res
+
+
+def leg_batched(args, torch, S, W, O):
+    cfg = W.config("batched1024")
+    g, cams, mlp = cfg["grid"], cfg["cams"], cfg["mlp"]
+    h = S.Handle()
+    dg = S.DeviceGrid(h, g.N, g.B, g.indirection, g.dens, g.rgb, g.feat)
+    m = S.mlp_tensor(mlp)
+    n = sum(c.n_rays for c in cams)
+    out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    carr = S.make_cameras(cams)
+    opts = S.make_opts(fp16=True, persistent=True, graph=True)
+    log(f"batched1024: {g.n_blocks} blocks, {len(cams)} cameras, {n} rays; autotuning")
+    best, best_ms = S.snerg_autotune(h, dg.struct(), m, carr, opts, out, reps=2)
+    log(f"batched1024: tuning {best} at {best_ms:.3f} ms")
+    grid = dg.struct()
+
+    def step():
+        S.snerg_render(h, grid, m, carr, None, n, opts, out)
+
+    steps = max(2, args.steps // 4)
+    ms = time_launches(step, steps, max(1, args.warmup), torch)
+    frame = out.cpu().numpy()
+    ids = np.sort(np.random.default_rng(3).choice(n, 4096, replace=False))
+    ref = O.render(O.OracleGrid(g), mlp, cams, ray_ids=ids)["rgba"]
+    err = float(np.abs(frame[ids] - ref).max())
+    res = dict(ms=ms, rays=n, mrays=n / ms / 1e3, max_abs_err=err, err_sample=len(ids), tuning=list(best))
+    log(f"batched1024: {ms:.3f} ms/batch, {res['mrays']:.1f} Mrays/s, fp16 max-abs err {err:.2e}")
+    return res
+
+
+def leg_adjoint(args, torch, S, W, O):
+    from paper_2103_14645_amd import autograd as A
+    cfg = W.config("adjoint512")
+    g, cams, mlp = cfg["grid"], cfg["cams"], cfg["mlp"]
+    h = S.Handle()
+    r = A.ShadowRenderer(h, g.N, g.B, g.indirection, g.n_blocks)
+    dens = torch.from_numpy(g.dens).cuda().float().div_(255.0)
+    rgb = torch.from_numpy(g.rgb).cuda().float().div_(255.0)
+    feat = torch.from_numpy(g.feat).cuda().float().div_(255.0)
+    m = S.mlp_tensor(mlp)
+    carr = S.make_cameras(cams)
+    n = sum(c.n_rays for c in cams)
+    opts = S.make_opts()
+    r.pack(dens, rgb, feat)
+    grid = r.struct()
+    out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    aux = torch.empty((n, 8), dtype=torch.float32, device="cuda")
+    S.snerg_render(h, grid, m, carr, None, n, opts, out, aux)
+    gout = torch.randn((n, 4), device="cuda") / n
+    gm = torch.empty(883, device="cuda")
+    gd, gr, gf = torch.empty_like(dens), torch.empty_like(rgb), torch.empty_like(feat)
+
+    def fwd():
+        S.snerg_render(h, grid, m, carr, None, n, opts, out, aux)
+
+    def bwd():
+        S.snerg_render_backward(h, grid, m, carr, None, n, opts, aux, gout, gm, gd, gr, gf)
+
+    log(f"adjoint512: {n} rays over {len(cams)} views")
+    steps = max(2, args.steps // 4)
+    ms_f = time_launches(fwd, steps, 1, torch)
+    ms_b = time_launches(bwd, steps, 1, torch)
+    res = dict(ms_fwd=ms_f, ms_bwd=ms_b, rays=n, fwd_mrays=n / ms_f / 1e3, bwd_mrays=n / ms_b / 1e3)
+    log(f"adjoint512: fwd {ms_f:.3f} ms, bwd {ms_b:.3f} ms -> {res['bwd_mrays']:.1f} bwd Mrays/s")
+    return res
+
+
+def cpu_baseline(plain, O):
+    """The FP64 oracle on the host cores, on every 4th ray of the 800x800 frame."""
+    n = plain["rays"]
+    ids = np.arange(0, n, 4, dtype=np.int64)
+    og = O.OracleGrid(plain["g"])
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    ref = O.render(og, plain["mlp"], plain["cams"], ray_ids=ids, threads=threads)["rgba"]
+    dt = time.perf_counter() - t0
+    err = float(np.abs(plain["out"].cpu().numpy()[ids] - ref).max())
+    return dict(value=len(ids) / dt / 1e6, unit="Mrays/s", cores=threads, kind="oracle",
+                sample=f"every 4th ray of the 800x800 frame ({len(ids)} rays), {dt:.1f} s",
+                gpu_max_abs_err=err)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--legs", default="plain,batched,adjoint")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the render shards by rays "
+              f"with no communication; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import oracle as O
+    import workloads as W
+    from paper_2103_14645_amd import snerg as S
+
+    torch.cuda.set_device(0)
+    legs = set(args.legs.split(","))
+    plain = leg_plain(args, torch, S, W, O)
+    extra = {}
+    if "batched" in legs:
+        extra["batched_fp16_1024"] = leg_batched(args, torch, S, W, O)
+    if "adjoint" in legs:
+        extra["adjoint_512"] = leg_adjoint(args, torch, S, W, O)
+
+    ms = plain["ms"]
+    achieved = plain["alg_bytes"] / (ms * 1e-3) / 1e9
+    line = {
+        "metric": "Mrays/s and fps at 800x800 (fwd, batched FP16-MLP vs plain FP32); bwd Mrays/s",
+        "value": round(plain["mrays"], 3),
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "plain512: 512^3 SNeRG, B=32, 10.6% occupied procedural shell, uint8 atlas, "
+                               "one 800x800 camera (39 deg), FP32 34-16-16-3 MLP",
+                   "fps_800x800": round(1000.0 / ms, 2), "rays": plain["rays"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_render<u8, fp32-mlp>", "alg_bytes_per_launch": plain["alg_bytes"],
+                     "counters": plain["counters"]},
+    }
+    legs_out = {}
+    if "batched_fp16_1024" in extra:
+        b = extra["batched_fp16_1024"]
+        legs_out["batched_fp16_1024"] = {"mrays": round(b["mrays"], 3), "ms": round(b["ms"], 4),
+                                         "fps_800x800_equiv": round(b["mrays"] / 0.64, 2),
+                                         "max_abs_err_vs_oracle": b["max_abs_err"], "err_sample": b["err_sample"],
+                                         "rays": b["rays"], "tuning": b["tuning"]}
+    if "adjoint_512" in extra:
+        a = extra["adjoint_512"]
+        legs_out["adjoint_512"] = {"bwd_mrays": round(a["bwd_mrays"], 3), "fwd_mrays": round(a["fwd_mrays"], 3),
+                                   "ms_bwd": round(a["ms_bwd"], 4), "ms_fwd": round(a["ms_fwd"], 4),
+                                   "rays": a["rays"]}
+    line["legs"] = legs_out
+    if not args.no_cpu_baseline:
+        log("cpu baseline (FP64 oracle)")
+        line["cpu_baseline"] = cpu_baseline(plain, O)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,229 @@
+/*
+ * snerg.h -- C ABI of the MI355X (gfx950) SNeRG renderer.
+ *
+ * Renders a Sparse Neural Radiance Grid as described in "Baking Neural
+ * Radiance Fields for Real-Time View Synthesis" (Hedman et al., arXiv
+ * 2103.14645): for every pixel a ray is marched through the block-sparse
+ * grid (Section 5.1: a coarse indirection grid over an atlas of B^3
+ * macroblocks holding density, diffuse colour and a 4-channel feature
+ * vector), trilinearly sampled and alpha-composited front to back with
+ * early termination (Section 5.2, Eq. 2, 5, 6); the deferred shading MLP
+ * then runs once per pixel on the composited colour, features and view
+ * direction and its residual is added (Eq. 7, Section 4.2).  A backward
+ * entry point gives gradients with respect to the MLP and a float copy of
+ * the grid values, for fine-tuning by a pixel loss (Eq. 3, Section 5.5).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Device pointers ("device") are HIP device allocations owned by the
+ *    caller; the library never allocates, frees or retains them.  Host
+ *    pointers ("host") are read during the call only.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  All device
+ *    work is enqueued asynchronously on it; results are valid once the
+ *    stream has reached that point.
+ *  - Validation is synchronous and host-only and happens before any device
+ *    work; a call that returns an error has enqueued nothing and written
+ *    nothing.  Device faults surface as SNERG_ERR_HIP at a later call or
+ *    at stream synchronisation.  No C++ exception crosses this ABI.
+ *  - Calls on one handle must not run concurrently from several host
+ *    threads.  Different handles are independent.
+ *
+ * Geometry (what every entry point computes)
+ * ------------------------------------------
+ *  - The grid covers the world box [-1, 1]^3 with N^3 voxels; voxel i spans
+ *    [i, i+1) in voxel units u = (x + 1) N / 2 and its value sits at its
+ *    centre.  Macroblocks are B^3 voxels; the indirection grid has
+ *    G^3 = (N/B)^3 int32 entries, x fastest ((bz*G + by)*G + bx): -1 marks
+ *    an empty macroblock, otherwise the entry is the macroblock's atlas id.
+ *  - Canonical atlas arrays (inputs of snerg_pack_grid, shapes of the grid
+ *    gradients): dens [n_blocks][B][B][B], rgb [n_blocks][B][B][B][3],
+ *    feat [n_blocks][B][B][B][4], voxel (x, y, z) of a block at
+ *    (z*B + y)*B + x.  SNERG_U8 values are bytes v with value v/255;
+ *    SNERG_F32 values are used as stored.  Density value s gives
+ *    sigma = sigma_scale * s (50 in the paper's setting of 8-bit density).
+ *  - Rays: pixel (i, j) of a W x H camera (column i, row j from the top)
+ *    has x = (i + 1/2 - W/2)/focal, y = (j + 1/2 - H/2)/focal and
+ *    direction d = D/|D|, D = fwd + x right - y up, computed in FP64 with
+ *    this exact operation order and no fused multiply-add.  Samples lie on
+ *    an integer lattice in Q16 fixed point from the camera centre:
+ *    o = rint(((eye + 1) (N/2)) 2^16), s = rint(d 2^15) (half a voxel),
+ *    P_k = o + k s for k = 0, 1, ...; a sample is inside the grid when
+ *    0 <= P_k < N 2^16 on every axis and is skipped when its macroblock
+ *    floor(P_k / (B 2^16)) is empty.
+ *  - Sampling: trilinear over the virtual dense grid (corner voxels outside
+ *    the grid or in empty macroblocks read 0), with Q = P_k - 2^15,
+ *    i0 = floor(Q / 2^16), f = (Q mod 2^16) / 2^16.  A sample is composited
+ *    only if some corner has non-zero density and non-zero weight.
+ *  - Compositing with step delta = 1/N: alpha = 1 - exp(-sigma delta),
+ *    w = T alpha, C_d += w c_d, V += w v, T *= 1 - alpha; with early stop
+ *    the march ends after the sample that brings T below t_stop.
+ *  - Deferred MLP (when mlp_on and at least one sample was composited):
+ *    x = [C_d(3), V(4), d(3), PE(d)(24)], PE octave l = 0..3:
+ *    sin(2^l pi d_xyz), cos(2^l pi d_xyz); R = sigmoid(W3 relu(W2 relu(W1 x
+ *    + b1) + b2) + b3).  Output rgb = C_d + T bg + R, alpha = 1 - T.
+ *  - Ray ids: cameras in order, rows from the top, columns left to right;
+ *    ray r of camera c has id offset_c + j W_c + i.
+ */
+#ifndef SNERG_H
+#define SNERG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+#define SNERG_OK 0
+#define SNERG_ERR_INVALID_ARG (-1) /* null pointer, bad size, NaN/Inf, non-orthonormal camera */
+#define SNERG_ERR_UNSUPPORTED (-2) /* B not a power of two, N % B != 0, unknown dtype/flag */
+#define SNERG_ERR_RANGE (-3)       /* lattice out of range: N > 16384 or an eye coordinate beyond +-1000 */
+#define SNERG_ERR_HIP (-4)         /* a HIP runtime call failed; see snerg_last_error() */
+#define SNERG_ERR_WORKSPACE (-5)   /* a caller-provided buffer is too small */
+
+/* -------------------------------------------------------------- grid types */
+#define SNERG_U8 0  /* 8-bit values (Section 5.4: all values quantised to 8 bits) */
+#define SNERG_F32 1 /* float32 values: the trainable shadow used by the backward pass */
+
+/* ------------------------------------------------------------- option flags */
+#define SNERG_FLAG_MLP_FP16 (1u << 0)   /* deferred MLP on FP16 MFMA tiles, FP32 accumulation */
+#define SNERG_FLAG_PERSISTENT (1u << 1) /* one persistent launch over a global tile queue */
+#define SNERG_FLAG_GRAPH (1u << 2)      /* replay the launch from a captured HIP graph */
+
+#define SNERG_MLP_PARAMS 883 /* W1[16][34] b1[16] W2[16][16] b2[16] W3[3][16] b3[3], [out][in] */
+
+typedef struct snerg_handle snerg_handle;
+
+/* A packed grid as the render kernels read it. */
+typedef struct {
+    int32_t N;                  /* voxels per axis, 1 <= N <= 16384 */
+    int32_t B;                  /* macroblock edge, power of two, 2 <= B <= 64, N % B == 0 */
+    int32_t n_blocks;           /* atlas macroblocks (>= 0) */
+    int32_t dtype;              /* SNERG_U8 or SNERG_F32 (of the packed values) */
+    const int32_t *indirection; /* device, (N/B)^3 entries as described above */
+    const void *packed;         /* device, written by snerg_pack_grid for the same N, B, n_blocks, dtype */
+    float sigma_scale;          /* sigma = sigma_scale * density value (50) */
+    int32_t reserved;
+} snerg_grid;
+
+/* Pinhole camera; fwd, right, up must be orthonormal (|.| within 1e-6). */
+typedef struct {
+    double eye[3], fwd[3], right[3], up[3];
+    int32_t W, H;  /* image size, >= 1 */
+    double focal;  /* focal length in pixels, > 0 */
+} snerg_camera;
+
+typedef struct {
+    float bg[3];        /* background colour added with weight T */
+    float t_stop;       /* early-stop threshold on T (1e-3) */
+    int32_t early_stop; /* 0/1 */
+    int32_t mlp_on;     /* 0/1: 0 renders the diffuse colour only */
+    uint32_t flags;     /* SNERG_FLAG_* */
+    int32_t reserved;
+} snerg_opts;
+
+/* Launch shape used by the forward kernels (chosen by snerg_autotune). */
+typedef struct {
+    int32_t tile_w, tile_h;   /* pixels per wavefront tile, tile_w * tile_h == 64 */
+    int32_t waves_per_group;  /* wavefronts per workgroup: 1, 2, 4 or 8 */
+    int32_t groups_per_cu;    /* persistent launch: resident workgroups per compute unit, 1..16 */
+} snerg_tuning;
+
+/* ---------------------------------------------------------------- handles */
+
+/* Creates a handle on the current HIP device.  It owns small device buffers
+ * (camera table, tile counter, reduction scratch), cached HIP graphs and
+ * the tuning table; nothing the caller passes in. */
+int snerg_create(snerg_handle **out);
+int snerg_destroy(snerg_handle *h);
+
+/* Static description of a status code; never NULL. */
+const char *snerg_status_string(int status);
+/* Message of the last failure on this host thread ("" if none). */
+const char *snerg_last_error(void);
+
+/* ---------------------------------------------------------------- packing */
+
+/* Bytes of the packed grid for the given shape (Section 5.1 data structure
+ * re-laid out for the GPU: per macroblock a copy of its B^3 voxels with a
+ * one-voxel apron taken from the neighbouring macroblocks, channels
+ * interleaved per voxel, plus a per-cell occupancy bitmask). */
+int snerg_packed_size(int32_t N, int32_t B, int32_t n_blocks, int32_t dtype, size_t *bytes);
+
+/* Builds the packed grid from canonical arrays.  indirection, dens, rgb,
+ * feat: device, canonical layout, element type given by dtype (uint8 or
+ * float32).  packed: device, at least snerg_packed_size() bytes. */
+int snerg_pack_grid(snerg_handle *h, int32_t N, int32_t B, int32_t n_blocks, int32_t dtype,
+                    const int32_t *indirection, const void *dens, const void *rgb, const void *feat,
+                    void *packed, size_t packed_bytes, void *stream);
+
+/* ------------------------------------------------------------- rendering */
+
+/*
+ * Renders rays (Section 5.2, Eq. 5-7).  cams: host, n_cams >= 1.  ray_ids:
+ * device int64 [n_rays] or NULL for every ray of every camera (then n_rays
+ * must equal the total pixel count).  mlp: device float32 [883] (may be
+ * NULL when opts->mlp_on == 0).  out_rgba: device float32 [n_rays][4].
+ * aux: device float32 [n_rays][8] or NULL; receives C_d[3], V[4] and T,
+ * with T replaced by -1 when no sample was composited (then T = 1).  The
+ * backward pass consumes aux.
+ */
+int snerg_render(snerg_handle *h, const snerg_grid *grid, const float *mlp, const snerg_camera *cams,
+                 int32_t n_cams, const int64_t *ray_ids, int64_t n_rays, const snerg_opts *opts,
+                 float *out_rgba, float *aux, void *stream);
+
+/*
+ * Gradient of L = sum_r grad_rgba[r] . rgba[r] (Eq. 3 fine-tuning, Section
+ * 5.5) with respect to the 883 MLP parameters and the float32 grid values,
+ * holding the set of composited samples and the stopping sample fixed.
+ * grid->dtype must be SNERG_F32.  Rays are re-marched (nothing per sample
+ * is stored); aux must come from snerg_render of the same rays, grid, MLP,
+ * cameras and options.  grad_rgba: device [n_rays][4].  Outputs (device,
+ * overwritten, not accumulated): grad_mlp [883], grad_dens, grad_rgb,
+ * grad_feat in canonical atlas layout.  Gradient sums use float32 atomics,
+ * so their rounding depends on scheduling.
+ */
+int snerg_render_backward(snerg_handle *h, const snerg_grid *grid, const float *mlp,
+                          const snerg_camera *cams, int32_t n_cams, const int64_t *ray_ids,
+                          int64_t n_rays, const snerg_opts *opts, const float *aux,
+                          const float *grad_rgba, float *grad_mlp, float *grad_dens,
+                          float *grad_rgb, float *grad_feat, void *stream);
+
+/*
+ * Occupied macroblocks each ray visits in order (linear indirection index,
+ * consecutive repeats collapsed), up to max_visits per ray, with the same
+ * march and stopping rule as snerg_render.  visits: device int32
+ * [n_rays][max_visits] (unused slots untouched; may be NULL when
+ * max_visits == 0); counts: device int32 [n_rays] (full count, may exceed
+ * max_visits); counters: device int32 [n_rays][5] or NULL = macroblocks
+ * traversed, occupied macroblocks visited, samples inside occupied
+ * macroblocks, composited samples, stopping k (-1 if none).
+ */
+int snerg_trace_visits(snerg_handle *h, const snerg_grid *grid, const snerg_camera *cams,
+                       int32_t n_cams, const int64_t *ray_ids, int64_t n_rays, const snerg_opts *opts,
+                       int32_t max_visits, int32_t *visits, int32_t *counts, int32_t *counters,
+                       void *stream);
+
+/* ---------------------------------------------------------------- tuning */
+
+int snerg_set_tuning(snerg_handle *h, const snerg_tuning *t);
+int snerg_get_tuning(snerg_handle *h, snerg_tuning *t);
+
+/*
+ * Times each candidate launch shape (HIP events, `reps` renders after one
+ * warm-up) for the given render call and keeps the fastest in the handle.
+ * candidates: host [n_candidates] or NULL for the built-in search space.
+ * out_rgba receives the last render.  best (host, nullable) receives the
+ * winner and best_ms its time per render.  Synchronises `stream`.
+ */
+int snerg_autotune(snerg_handle *h, const snerg_grid *grid, const float *mlp,
+                   const snerg_camera *cams, int32_t n_cams, const snerg_opts *opts,
+                   const snerg_tuning *candidates, int32_t n_candidates, int32_t reps,
+                   float *out_rgba, snerg_tuning *best, float *best_ms, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SNERG_H */

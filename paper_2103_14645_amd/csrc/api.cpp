@@ -1,0 +1,546 @@
+// C ABI of the gfx950 SNeRG renderer: argument validation (host only, before
+// any device work), the handle's small device buffers, launch planning,
+// HIP-graph replay of the persistent launch and the launch-shape autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "snerg.h"
+#include "snerg_launch.h"
+
+using namespace snerg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(SNERG_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+bool finite3(const double v[3]) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int check_shape(int32_t N, int32_t B, int32_t n_blocks, int32_t dtype) {
+    if (dtype != SNERG_U8 && dtype != SNERG_F32) return fail(SNERG_ERR_UNSUPPORTED, "dtype must be SNERG_U8 or SNERG_F32");
+    if (!is_pow2(B) || B < 2 || B > 64) return fail(SNERG_ERR_UNSUPPORTED, "B must be a power of two in [2, 64]");
+    if (N < 1) return fail(SNERG_ERR_INVALID_ARG, "N must be >= 1");
+    if (N % B != 0) return fail(SNERG_ERR_UNSUPPORTED, "N must be a multiple of B");
+    if (N > 16384) return fail(SNERG_ERR_RANGE, "N > 16384 overflows the Q16 lattice in int32");
+    if (n_blocks < 0) return fail(SNERG_ERR_INVALID_ARG, "n_blocks must be >= 0");
+    const int64_t G = N / B;
+    if (n_blocks > G * G * G) return fail(SNERG_ERR_INVALID_ARG, "n_blocks exceeds (N/B)^3");
+    return SNERG_OK;
+}
+
+int check_grid(const snerg_grid* g) {
+    if (!g) return fail(SNERG_ERR_INVALID_ARG, "grid is NULL");
+    int rc = check_shape(g->N, g->B, g->n_blocks, g->dtype);
+    if (rc) return rc;
+    if (!g->indirection) return fail(SNERG_ERR_INVALID_ARG, "grid->indirection is NULL");
+    if (!g->packed && g->n_blocks > 0) return fail(SNERG_ERR_INVALID_ARG, "grid->packed is NULL");
+    if (!std::isfinite(g->sigma_scale) || g->sigma_scale < 0.0f)
+        return fail(SNERG_ERR_INVALID_ARG, "sigma_scale must be finite and >= 0");
+    return SNERG_OK;
+}
+
+int check_cams(const snerg_camera* cams, int32_t n_cams, int64_t* total) {
+    if (!cams) return fail(SNERG_ERR_INVALID_ARG, "cams is NULL");
+    if (n_cams < 1) return fail(SNERG_ERR_INVALID_ARG, "n_cams must be >= 1");
+    int64_t t = 0;
+    for (int32_t c = 0; c < n_cams; ++c) {
+        const snerg_camera& k = cams[c];
+        char buf[96];
+        std::snprintf(buf, sizeof buf, "camera %d: ", c);
+        if (k.W < 1 || k.H < 1) return fail(SNERG_ERR_INVALID_ARG, std::string(buf) + "W and H must be >= 1");
+        if (int64_t(k.W) * k.H > (int64_t(1) << 31)) return fail(SNERG_ERR_INVALID_ARG, std::string(buf) + "W*H > 2^31");
+        if (!std::isfinite(k.focal) || k.focal <= 0.0) return fail(SNERG_ERR_INVALID_ARG, std::string(buf) + "focal must be finite and > 0");
+        if (!finite3(k.eye) || !finite3(k.fwd) || !finite3(k.right) || !finite3(k.up))
+            return fail(SNERG_ERR_INVALID_ARG, std::string(buf) + "non-finite camera vector");
+        const double tol = 1e-6;
+        if (std::fabs(dot3(k.fwd, k.fwd) - 1) > tol || std::fabs(dot3(k.right, k.right) - 1) > tol ||
+            std::fabs(dot3(k.up, k.up) - 1) > tol || std::fabs(dot3(k.fwd, k.right)) > tol ||
+            std::fabs(dot3(k.fwd, k.up)) > tol || std::fabs(dot3(k.right, k.up)) > tol)
+            return fail(SNERG_ERR_INVALID_ARG, std::string(buf) + "fwd/right/up must be orthonormal");
+        for (int a = 0; a < 3; ++a)
+            if (std::fabs(k.eye[a]) > 1000.0) return fail(SNERG_ERR_RANGE, std::string(buf) + "|eye| > 1000");
+        t += int64_t(k.W) * k.H;
+    }
+    *total = t;
+    return SNERG_OK;
+}
+
+int check_opts(const snerg_opts* o) {
+    if (!o) return fail(SNERG_ERR_INVALID_ARG, "opts is NULL");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(o->bg[a])) return fail(SNERG_ERR_INVALID_ARG, "opts->bg must be finite");
+    if (!std::isfinite(o->t_stop) || o->t_stop < 0.0f) return fail(SNERG_ERR_INVALID_ARG, "opts->t_stop must be finite and >= 0");
+    const uint32_t known = SNERG_FLAG_MLP_FP16 | SNERG_FLAG_PERSISTENT | SNERG_FLAG_GRAPH;
+    if (o->flags & ~known) return fail(SNERG_ERR_UNSUPPORTED, "unknown opts->flags bits");
+    return SNERG_OK;
+}
+
+int check_tuning(const snerg_tuning* t) {
+    if (!t) return fail(SNERG_ERR_INVALID_ARG, "tuning is NULL");
+    if (t->tile_w < 1 || t->tile_h < 1 || t->tile_w * t->tile_h != 64)
+        return fail(SNERG_ERR_INVALID_ARG, "tile_w * tile_h must be 64");
+    if (t->waves_per_group != 1 && t->waves_per_group != 2 && t->waves_per_group != 4)
+        return fail(SNERG_ERR_INVALID_ARG, "waves_per_group must be 1, 2 or 4");
+    if (t->groups_per_cu < 1 || t->groups_per_cu > 16) return fail(SNERG_ERR_INVALID_ARG, "groups_per_cu must be in [1, 16]");
+    return SNERG_OK;
+}
+
+GridArgs grid_args(const snerg_grid* g) {
+    const PackedLayout L = make_layout(g->N, g->B, g->n_blocks, g->dtype == SNERG_F32 ? 32 : 8);
+    const uint8_t* p = static_cast<const uint8_t*>(g->packed);
+    GridArgs a;
+    a.ind = g->indirection;
+    a.block_lin = reinterpret_cast<const int32_t*>(p + L.off_lin);
+    a.mask = reinterpret_cast<const uint32_t*>(p + L.off_mask);
+    a.vox = p + L.off_vox;
+    a.N = L.N; a.B = L.B; a.logB = L.logB; a.G = L.G; a.Bp = L.Bp; a.Bc = L.Bc;
+    a.mask_words = L.mask_words;
+    a.n_blocks = g->n_blocks;
+    a.vox_stride = L.vox_stride;
+    a.sigma_scale = g->sigma_scale;
+    return a;
+}
+
+RenderOpts render_opts(const snerg_opts* o) {
+    RenderOpts r;
+    for (int a = 0; a < 3; ++a) r.bg[a] = o->bg[a];
+    r.t_stop = o->t_stop;
+    r.early_stop = o->early_stop ? 1 : 0;
+    r.mlp_on = o->mlp_on ? 1 : 0;
+    return r;
+}
+
+}  // namespace
+
+struct snerg_handle {
+    int device = 0;
+    int n_cu = 256;
+    hipStream_t cap_stream = nullptr;
+    DevCamera* d_cams = nullptr;
+    size_t cams_cap = 0;
+    DevCamera* h_cams = nullptr;  // pinned staging
+    hipEvent_t cams_copied = nullptr;
+    bool cams_pending = false;
+    std::vector<DevCamera> last_cams;
+    int32_t* d_counter = nullptr;
+    float* d_partial = nullptr;
+    size_t partial_cap = 0;
+    snerg_tuning tuning = {8, 8, 4, 8};
+    // cached graph of {counter reset, persistent render}
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<uint8_t> graph_key;
+};
+
+namespace {
+
+// Camera table for the current call: uploaded only when it changed.
+int upload_cams(snerg_handle* h, const snerg_camera* cams, int32_t n_cams, int tile_w, int tile_h,
+                hipStream_t s, int64_t* total_tiles) {
+    std::vector<DevCamera> t(n_cams);
+    int64_t rays = 0, tiles = 0;
+    for (int32_t c = 0; c < n_cams; ++c) {
+        DevCamera& d = t[c];
+        std::memset(&d, 0, sizeof d);
+        for (int a = 0; a < 3; ++a) {
+            d.eye[a] = cams[c].eye[a];
+            d.fwd[a] = cams[c].fwd[a];
+            d.right[a] = cams[c].right[a];
+            d.up[a] = cams[c].up[a];
+        }
+        d.focal = cams[c].focal;
+        d.W = cams[c].W;
+        d.H = cams[c].H;
+        d.ray_offset = rays;
+        d.tile_offset = tiles;
+        d.tiles_x = (cams[c].W + tile_w - 1) / tile_w;
+        d.tiles_y = (cams[c].H + tile_h - 1) / tile_h;
+        rays += int64_t(cams[c].W) * cams[c].H;
+        tiles += int64_t(d.tiles_x) * d.tiles_y;
+    }
+    *total_tiles = tiles;
+    if (h->last_cams.size() == t.size() &&
+        std::memcmp(h->last_cams.data(), t.data(), t.size() * sizeof(DevCamera)) == 0)
+        return SNERG_OK;
+    if (size_t(n_cams) > h->cams_cap) {
+        if (h->cams_pending) HIP_TRY(hipEventSynchronize(h->cams_copied));
+        h->cams_pending = false;
+        if (h->d_cams) HIP_TRY(hipFree(h->d_cams));
+        if (h->h_cams) HIP_TRY(hipHostFree(h->h_cams));
+        h->d_cams = nullptr;
+        h->h_cams = nullptr;
+        h->graph_key.clear();
+        size_t cap = std::max<size_t>(64, size_t(n_cams));
+        HIP_TRY(hipMalloc(&h->d_cams, cap * sizeof(DevCamera)));
+        HIP_TRY(hipHostMalloc(&h->h_cams, cap * sizeof(DevCamera), hipHostMallocDefault));
+        h->cams_cap = cap;
+    }
+    if (h->cams_pending) HIP_TRY(hipEventSynchronize(h->cams_copied));  // staging buffer reuse
+    std::memcpy(h->h_cams, t.data(), t.size() * sizeof(DevCamera));
+    HIP_TRY(hipMemcpyAsync(h->d_cams, h->h_cams, t.size() * sizeof(DevCamera), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(h->cams_copied, s));
+    h->cams_pending = true;
+    h->last_cams = t;
+    return SNERG_OK;
+}
+
+int ensure_partial(snerg_handle* h, size_t rows) {
+    const size_t need = rows * kMlpParams;
+    if (need <= h->partial_cap) return SNERG_OK;
+    HIP_TRY(hipDeviceSynchronize());
+    if (h->d_partial) HIP_TRY(hipFree(h->d_partial));
+    h->d_partial = nullptr;
+    HIP_TRY(hipMalloc(&h->d_partial, need * sizeof(float)));
+    h->partial_cap = need;
+    return SNERG_OK;
+}
+
+// Shared checks; n_rays < 0 means "all rays" (the caller passes no count).
+int common_render_checks(const snerg_grid* grid, const float* mlp, bool need_mlp, const snerg_camera* cams,
+                         int32_t n_cams, const int64_t* ray_ids, int64_t n_rays, const snerg_opts* opts,
+                         int64_t* total) {
+    int rc;
+    if ((rc = check_grid(grid))) return rc;
+    if ((rc = check_cams(cams, n_cams, total))) return rc;
+    if ((rc = check_opts(opts))) return rc;
+    if (need_mlp && opts->mlp_on && !mlp) return fail(SNERG_ERR_INVALID_ARG, "mlp is NULL while opts->mlp_on");
+    if (ray_ids && n_rays < 0) return fail(SNERG_ERR_INVALID_ARG, "n_rays must be >= 0");
+    if (!ray_ids && n_rays >= 0 && n_rays != *total)
+        return fail(SNERG_ERR_INVALID_ARG, "without ray_ids, n_rays must equal the total pixel count");
+    return SNERG_OK;
+}
+
+int render_impl(snerg_handle* h, const snerg_grid* grid, const float* mlp, const snerg_camera* cams,
+                int32_t n_cams, const int64_t* ray_ids, int64_t n_rays, const snerg_opts* opts,
+                float* out_rgba, float* aux, hipStream_t s, const snerg_tuning& tu) {
+    RenderArgs a;
+    std::memset(&a, 0, sizeof a);
+    int64_t total_tiles = 0;
+    int rc = upload_cams(h, cams, n_cams, tu.tile_w, tu.tile_h, s, &total_tiles);
+    if (rc) return rc;
+    a.grid = grid_args(grid);
+    a.opts = render_opts(opts);
+    a.mlp = mlp;
+    a.cams = h->d_cams;
+    a.n_cams = n_cams;
+    a.ray_ids = ray_ids;
+    a.n_rays = n_rays;
+    a.total_tiles = total_tiles;
+    a.tile_w = tu.tile_w;
+    a.tile_h = tu.tile_h;
+    a.tile_counter = h->d_counter;
+    a.out = out_rgba;
+    a.aux = aux;
+    const int vt = grid->dtype == SNERG_F32 ? 1 : 0;
+    const int mlp_mode = !opts->mlp_on ? kMlpOff : ((opts->flags & SNERG_FLAG_MLP_FP16) ? kMlpF16 : kMlpF32);
+    const int wpg = tu.waves_per_group;
+    if (ray_ids) {
+        a.mode = kModeList;
+        HIP_TRY(launch_render(a, vt, mlp_mode, wpg, 0, s));
+        return SNERG_OK;
+    }
+    if (!(opts->flags & SNERG_FLAG_PERSISTENT)) {
+        a.mode = kModeTiles;
+        HIP_TRY(launch_render(a, vt, mlp_mode, wpg, 0, s));
+        return SNERG_OK;
+    }
+    a.mode = kModePersistent;
+    const int n_groups = h->n_cu * tu.groups_per_cu;
+    if (!(opts->flags & SNERG_FLAG_GRAPH)) {
+        HIP_TRY(launch_fill_i32(h->d_counter, 1, 0, s));
+        HIP_TRY(launch_render(a, vt, mlp_mode, wpg, n_groups, s));
+        return SNERG_OK;
+    }
+    // Graph replay: the key is every launch parameter; the camera table's
+    // contents live in device memory outside the graph.
+    std::vector<uint8_t> key(sizeof a + 3 * sizeof(int));
+    std::memcpy(key.data(), &a, sizeof a);
+    const int extra[3] = {vt, mlp_mode, wpg * 1000 + n_groups};
+    std::memcpy(key.data() + sizeof a, extra, sizeof extra);
+    if (!h->graph_exec || key != h->graph_key) {
+        if (h->graph_exec) {
+            HIP_TRY(hipStreamSynchronize(s));
+            HIP_TRY(hipGraphExecDestroy(h->graph_exec));
+            h->graph_exec = nullptr;
+        }
+        hipGraph_t graph = nullptr;
+        HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e1 = launch_fill_i32(h->d_counter, 1, 0, h->cap_stream);
+        hipError_t e2 = e1 == hipSuccess ? launch_render(a, vt, mlp_mode, wpg, n_groups, h->cap_stream) : e1;
+        hipError_t e3 = hipStreamEndCapture(h->cap_stream, &graph);
+        if (e2 != hipSuccess) {
+            if (graph) hipGraphDestroy(graph);
+            return fail(SNERG_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e2));
+        }
+        HIP_TRY(e3);
+        hipError_t e4 = hipGraphInstantiate(&h->graph_exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        HIP_TRY(e4);
+        h->graph_key = key;
+    }
+    HIP_TRY(hipGraphLaunch(h->graph_exec, s));
+    return SNERG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* snerg_status_string(int status) {
+    switch (status) {
+    case SNERG_OK: return "ok";
+    case SNERG_ERR_INVALID_ARG: return "invalid argument";
+    case SNERG_ERR_UNSUPPORTED: return "unsupported configuration";
+    case SNERG_ERR_RANGE: return "fixed-point range exceeded";
+    case SNERG_ERR_HIP: return "HIP runtime error";
+    case SNERG_ERR_WORKSPACE: return "buffer too small";
+    default: return "unknown status";
+    }
+}
+
+const char* snerg_last_error(void) { return g_last_error.c_str(); }
+
+int snerg_create(snerg_handle** out) {
+    if (!out) return fail(SNERG_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    snerg_handle* h = new (std::nothrow) snerg_handle();
+    if (!h) return fail(SNERG_ERR_INVALID_ARG, "out of host memory");
+    hipError_t e = hipGetDevice(&h->device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, h->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->cams_copied, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMalloc(&h->d_counter, 256);
+    if (e != hipSuccess) {
+        snerg_destroy(h);
+        return fail(SNERG_ERR_HIP, std::string("snerg_create: ") + hipGetErrorString(e));
+    }
+    *out = h;
+    return SNERG_OK;
+}
+
+int snerg_destroy(snerg_handle* h) {
+    if (!h) return SNERG_OK;
+    if (h->cams_pending) hipEventSynchronize(h->cams_copied);
+    if (h->graph_exec) hipGraphExecDestroy(h->graph_exec);
+    if (h->d_cams) hipFree(h->d_cams);
+    if (h->h_cams) hipHostFree(h->h_cams);
+    if (h->d_counter) hipFree(h->d_counter);
+    if (h->d_partial) hipFree(h->d_partial);
+    if (h->cams_copied) hipEventDestroy(h->cams_copied);
+    if (h->cap_stream) hipStreamDestroy(h->cap_stream);
+    delete h;
+    return SNERG_OK;
+}
+
+int snerg_packed_size(int32_t N, int32_t B, int32_t n_blocks, int32_t dtype, size_t* bytes) {
+    if (!bytes) return fail(SNERG_ERR_INVALID_ARG, "bytes is NULL");
+    int rc = check_shape(N, B, n_blocks, dtype);
+    if (rc) return rc;
+    *bytes = size_t(make_layout(N, B, n_blocks, dtype == SNERG_F32 ? 32 : 8).total);
+    return SNERG_OK;
+}
+
+int snerg_pack_grid(snerg_handle* h, int32_t N, int32_t B, int32_t n_blocks, int32_t dtype,
+                    const int32_t* indirection, const void* dens, const void* rgb, const void* feat,
+                    void* packed, size_t packed_bytes, void* stream) {
+    int rc = check_shape(N, B, n_blocks, dtype);
+    if (rc) return rc;
+    if (!indirection || !packed) return fail(SNERG_ERR_INVALID_ARG, "indirection/packed is NULL");
+    if (n_blocks > 0 && (!dens || !rgb || !feat)) return fail(SNERG_ERR_INVALID_ARG, "dens/rgb/feat is NULL");
+    const PackedLayout L = make_layout(N, B, n_blocks, dtype == SNERG_F32 ? 32 : 8);
+    if (packed_bytes < size_t(L.total)) return fail(SNERG_ERR_WORKSPACE, "packed buffer smaller than snerg_packed_size()");
+    if (!h) return fail(SNERG_ERR_INVALID_ARG, "handle is NULL");
+    HIP_TRY(launch_pack(L, n_blocks, dtype == SNERG_F32, indirection, dens, rgb, feat,
+                        static_cast<uint8_t*>(packed), static_cast<hipStream_t>(stream)));
+    return SNERG_OK;
+}
+
+int snerg_render(snerg_handle* h, const snerg_grid* grid, const float* mlp, const snerg_camera* cams,
+                 int32_t n_cams, const int64_t* ray_ids, int64_t n_rays, const snerg_opts* opts,
+                 float* out_rgba, float* aux, void* stream) {
+    int64_t total = 0;
+    if (n_rays < 0) return fail(SNERG_ERR_INVALID_ARG, "n_rays must be >= 0");
+    int rc = common_render_checks(grid, mlp, true, cams, n_cams, ray_ids, n_rays, opts, &total);
+    if (rc) return rc;
+    if (!out_rgba) return fail(SNERG_ERR_INVALID_ARG, "out_rgba is NULL");
+    if (!h) return fail(SNERG_ERR_INVALID_ARG, "handle is NULL");
+    if (n_rays == 0) return SNERG_OK;
+    return render_impl(h, grid, mlp, cams, n_cams, ray_ids, n_rays, opts, out_rgba, aux,
+                       static_cast<hipStream_t>(stream), h->tuning);
+}
+
+int snerg_trace_visits(snerg_handle* h, const snerg_grid* grid, const snerg_camera* cams, int32_t n_cams,
+                       const int64_t* ray_ids, int64_t n_rays, const snerg_opts* opts, int32_t max_visits,
+                       int32_t* visits, int32_t* counts, int32_t* counters, void* stream) {
+    int64_t total = 0;
+    if (n_rays < 0) return fail(SNERG_ERR_INVALID_ARG, "n_rays must be >= 0");
+    int rc = common_render_checks(grid, nullptr, false, cams, n_cams, ray_ids, n_rays, opts, &total);
+    if (rc) return rc;
+    if (max_visits < 0) return fail(SNERG_ERR_INVALID_ARG, "max_visits must be >= 0");
+    if (max_visits > 0 && !visits) return fail(SNERG_ERR_INVALID_ARG, "visits is NULL");
+    if (!counts) return fail(SNERG_ERR_INVALID_ARG, "counts is NULL");
+    if (!h) return fail(SNERG_ERR_INVALID_ARG, "handle is NULL");
+    if (n_rays == 0) return SNERG_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int64_t total_tiles = 0;
+    rc = upload_cams(h, cams, n_cams, h->tuning.tile_w, h->tuning.tile_h, s, &total_tiles);
+    if (rc) return rc;
+    RenderArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.grid = grid_args(grid);
+    a.opts = render_opts(opts);
+    a.cams = h->d_cams;
+    a.n_cams = n_cams;
+    a.ray_ids = ray_ids;
+    a.n_rays = n_rays;
+    a.visits = visits;
+    a.max_visits = max_visits;
+    a.counts = counts;
+    a.counters = counters;
+    HIP_TRY(launch_trace(a, grid->dtype == SNERG_F32 ? 1 : 0, s));
+    return SNERG_OK;
+}
+
+int snerg_render_backward(snerg_handle* h, const snerg_grid* grid, const float* mlp, const snerg_camera* cams,
+                          int32_t n_cams, const int64_t* ray_ids, int64_t n_rays, const snerg_opts* opts,
+                          const float* aux, const float* grad_rgba, float* grad_mlp, float* grad_dens,
+                          float* grad_rgb, float* grad_feat, void* stream) {
+    int64_t total = 0;
+    if (n_rays < 0) return fail(SNERG_ERR_INVALID_ARG, "n_rays must be >= 0");
+    int rc = common_render_checks(grid, mlp, true, cams, n_cams, ray_ids, n_rays, opts, &total);
+    if (rc) return rc;
+    if (grid->dtype != SNERG_F32) return fail(SNERG_ERR_UNSUPPORTED, "the backward pass needs a SNERG_F32 grid");
+    if (opts->flags & SNERG_FLAG_MLP_FP16) return fail(SNERG_ERR_UNSUPPORTED, "FP16 MLP backward is not available");
+    if (!aux || !grad_rgba) return fail(SNERG_ERR_INVALID_ARG, "aux/grad_rgba is NULL");
+    if (!grad_mlp || !grad_dens || !grad_rgb || !grad_feat) return fail(SNERG_ERR_INVALID_ARG, "a gradient output is NULL");
+    if (!h) return fail(SNERG_ERR_INVALID_ARG, "handle is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t B3 = int64_t(grid->B) * grid->B * grid->B;
+    const int64_t nv = int64_t(grid->n_blocks) * B3;
+    const int waves = 4;
+    int64_t want = (n_rays + 64 * waves - 1) / (64 * waves);
+    const int n_groups = int(std::max<int64_t>(1, std::min<int64_t>(want, int64_t(h->n_cu) * 4)));
+    const int mlp_mode = opts->mlp_on ? kMlpF32 : kMlpOff;
+    if (mlp_mode != kMlpOff) {
+        rc = ensure_partial(h, size_t(n_groups) * waves);
+        if (rc) return rc;
+    }
+    int64_t total_tiles = 0;
+    rc = upload_cams(h, cams, n_cams, h->tuning.tile_w, h->tuning.tile_h, s, &total_tiles);
+    if (rc) return rc;
+    HIP_TRY(launch_fill_f32(grad_dens, nv, 0.0f, s));
+    HIP_TRY(launch_fill_f32(grad_rgb, nv * 3, 0.0f, s));
+    HIP_TRY(launch_fill_f32(grad_feat, nv * 4, 0.0f, s));
+    HIP_TRY(launch_fill_f32(grad_mlp, kMlpParams, 0.0f, s));
+    if (n_rays == 0) return SNERG_OK;
+    BackwardArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.grid = grid_args(grid);
+    a.opts = render_opts(opts);
+    a.mlp = mlp;
+    a.cams = h->d_cams;
+    a.n_cams = n_cams;
+    a.mlp_mode = mlp_mode;
+    a.ray_ids = ray_ids;
+    a.n_rays = n_rays;
+    a.aux = aux;
+    a.grad_rgba = grad_rgba;
+    a.g_mlp_partial = h->d_partial;
+    a.grad_dens = grad_dens;
+    a.grad_rgb = grad_rgb;
+    a.grad_feat = grad_feat;
+    HIP_TRY(launch_backward(a, n_groups, s));
+    if (mlp_mode != kMlpOff) HIP_TRY(launch_reduce_mlp(h->d_partial, n_groups * waves, grad_mlp, s));
+    return SNERG_OK;
+}
+
+int snerg_set_tuning(snerg_handle* h, const snerg_tuning* t) {
+    int rc = check_tuning(t);
+    if (rc) return rc;
+    h->tuning = *t;
+    return SNERG_OK;
+}
+
+int snerg_get_tuning(snerg_handle* h, snerg_tuning* t) {
+    if (!h || !t) return fail(SNERG_ERR_INVALID_ARG, "handle/tuning is NULL");
+    *t = h->tuning;
+    return SNERG_OK;
+}
+
+int snerg_autotune(snerg_handle* h, const snerg_grid* grid, const float* mlp, const snerg_camera* cams,
+                   int32_t n_cams, const snerg_opts* opts, const snerg_tuning* candidates, int32_t n_candidates,
+                   int32_t reps, float* out_rgba, snerg_tuning* best, float* best_ms, void* stream) {
+    int64_t total = 0;
+    int rc = common_render_checks(grid, mlp, true, cams, n_cams, nullptr, -1, opts, &total);
+    if (rc) return rc;
+    if (!out_rgba) return fail(SNERG_ERR_INVALID_ARG, "out_rgba is NULL");
+    if (reps < 1) return fail(SNERG_ERR_INVALID_ARG, "reps must be >= 1");
+    std::vector<snerg_tuning> cand;
+    if (candidates) {
+        if (n_candidates < 1) return fail(SNERG_ERR_INVALID_ARG, "n_candidates must be >= 1");
+        for (int i = 0; i < n_candidates; ++i) {
+            if ((rc = check_tuning(&candidates[i]))) return rc;
+            cand.push_back(candidates[i]);
+        }
+    } else {
+        const int shapes[4][2] = {{8, 8}, {16, 4}, {4, 16}, {32, 2}};
+        const int wpgs[3] = {1, 2, 4};
+        const int gpcs[3] = {2, 4, 8};
+        const bool persistent = (opts->flags & SNERG_FLAG_PERSISTENT) != 0;
+        for (auto& sh : shapes)
+            for (int w : wpgs)
+                for (int gi = 0; gi < (persistent ? 3 : 1); ++gi)
+                    cand.push_back(snerg_tuning{sh[0], sh[1], w, persistent ? gpcs[gi] : 8});
+    }
+    if (!h) return fail(SNERG_ERR_INVALID_ARG, "handle is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best_t = 1e30f;
+    snerg_tuning best_c = cand[0];
+    for (const snerg_tuning& c : cand) {
+        rc = render_impl(h, grid, mlp, cams, n_cams, nullptr, total, opts, out_rgba, nullptr, s, c);
+        if (rc) break;
+        HIP_TRY(hipEventRecord(e0, s));
+        for (int r = 0; r < reps && !rc; ++r)
+            rc = render_impl(h, grid, mlp, cams, n_cams, nullptr, total, opts, out_rgba, nullptr, s, c);
+        if (rc) break;
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        ms /= float(reps);
+        if (ms < best_t) {
+            best_t = ms;
+            best_c = c;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    h->tuning = best_c;
+    if (best) *best = best_c;
+    if (best_ms) *best_ms = best_t;
+    return render_impl(h, grid, mlp, cams, n_cams, nullptr, total, opts, out_rgba, nullptr, s, best_c);
+}
+
+}  // extern "C"

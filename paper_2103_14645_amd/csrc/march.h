@@ -1,0 +1,172 @@
+// The per-ray march shared by the forward, trace and backward kernels:
+// integer lattice traversal with macroblock skipping, the cell-mask
+// pre-test, the 8-corner gather from the padded block, the exact
+// active-sample predicate and trilinear weights.
+#pragma once
+
+#include "snerg_dev.h"
+
+namespace snerg {
+
+// One trilinear sample: weights, corner values and the exact active flag.
+struct Sample {
+    float sigma_raw;  // sum_c w_c * density_c (stored units)
+    float rgb[3];     // sum_c w_c * rgb_c (stored units)
+    float feat[4];
+    bool active;
+};
+
+__device__ __forceinline__ uint2 ld_u2(const uint8_t* p) {
+    return *reinterpret_cast<const uint2*>(p);
+}
+
+__device__ __forceinline__ float ubyte(uint32_t v, int i) {
+    return float((v >> (8 * i)) & 0xFFu);
+}
+
+// Corner weights from 16-bit fractions; order c = cx + 2 cy + 4 cz, product (wx*wy)*wz.
+__device__ __forceinline__ void corner_weights(const int32_t fr[3], float w[8]) {
+    const float fx = float(fr[0]) * (1.0f / 65536.0f);
+    const float fy = float(fr[1]) * (1.0f / 65536.0f);
+    const float fz = float(fr[2]) * (1.0f / 65536.0f);
+    const float gx = 1.0f - fx, gy = 1.0f - fy, gz = 1.0f - fz;
+    w[0] = (gx * gy) * gz;
+    w[1] = (fx * gy) * gz;
+    w[2] = (gx * fy) * gz;
+    w[3] = (fx * fy) * gz;
+    w[4] = (gx * gy) * fz;
+    w[5] = (fx * gy) * fz;
+    w[6] = (gx * fy) * fz;
+    w[7] = (fx * fy) * fz;
+}
+
+// Corner c may have non-zero weight: every axis with c_a = 1 needs f_a != 0.
+__device__ __forceinline__ bool corner_live(int c, const int32_t fr[3]) {
+    return ((c & 1) == 0 || fr[0] != 0) && ((c & 2) == 0 || fr[1] != 0) && ((c & 4) == 0 || fr[2] != 0);
+}
+
+// Gather at padded cell p (each in [0, B]) of a uint8 block.
+__device__ __forceinline__ void gather_u8(const uint8_t* __restrict__ blk, int Bp, const int32_t p[3],
+                                          const int32_t fr[3], Sample& smp) {
+    const uint8_t* base = blk + (int64_t((p[2] * Bp + p[1]) * Bp + p[0]) << 3);
+    const int sy = Bp * 8, sz = Bp * Bp * 8;
+    uint2 v[8];
+    v[0] = ld_u2(base);
+    v[1] = ld_u2(base + 8);
+    v[2] = ld_u2(base + sy);
+    v[3] = ld_u2(base + sy + 8);
+    v[4] = ld_u2(base + sz);
+    v[5] = ld_u2(base + sz + 8);
+    v[6] = ld_u2(base + sz + sy);
+    v[7] = ld_u2(base + sz + sy + 8);
+    float w[8];
+    corner_weights(fr, w);
+    float sd = 0.f, r0 = 0.f, r1 = 0.f, r2 = 0.f, f0 = 0.f, f1 = 0.f, f2 = 0.f, f3 = 0.f;
+    bool act = false;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        act |= ((v[c].x & 0xFFu) != 0u) && corner_live(c, fr);
+        sd += w[c] * ubyte(v[c].x, 0);
+        r0 += w[c] * ubyte(v[c].x, 1);
+        r1 += w[c] * ubyte(v[c].x, 2);
+        r2 += w[c] * ubyte(v[c].x, 3);
+        f0 += w[c] * ubyte(v[c].y, 0);
+        f1 += w[c] * ubyte(v[c].y, 1);
+        f2 += w[c] * ubyte(v[c].y, 2);
+        f3 += w[c] * ubyte(v[c].y, 3);
+    }
+    smp.sigma_raw = sd;
+    smp.rgb[0] = r0; smp.rgb[1] = r1; smp.rgb[2] = r2;
+    smp.feat[0] = f0; smp.feat[1] = f1; smp.feat[2] = f2; smp.feat[3] = f3;
+    smp.active = act;
+}
+
+// Gather at padded cell p of a float32 block (32 bytes per voxel).
+__device__ __forceinline__ void gather_f32(const uint8_t* __restrict__ blk, int Bp, const int32_t p[3],
+                                           const int32_t fr[3], Sample& smp) {
+    const float4* base = reinterpret_cast<const float4*>(blk) + (int64_t((p[2] * Bp + p[1]) * Bp + p[0]) << 1);
+    const int sy = Bp * 2, sz = Bp * Bp * 2;
+    float w[8];
+    corner_weights(fr, w);
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    bool act = false;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const float4* q = base + ((c & 4) ? sz : 0) + ((c & 2) ? sy : 0) + ((c & 1) ? 2 : 0);
+        const float4 a = q[0], b = q[1];
+        act |= (a.x != 0.f) && corner_live(c, fr);
+        acc[0] += w[c] * a.x; acc[1] += w[c] * a.y; acc[2] += w[c] * a.z; acc[3] += w[c] * a.w;
+        acc[4] += w[c] * b.x; acc[5] += w[c] * b.y; acc[6] += w[c] * b.z; acc[7] += w[c] * b.w;
+    }
+    smp.sigma_raw = acc[0];
+    smp.rgb[0] = acc[1]; smp.rgb[1] = acc[2]; smp.rgb[2] = acc[3];
+    smp.feat[0] = acc[4]; smp.feat[1] = acc[5]; smp.feat[2] = acc[6]; smp.feat[3] = acc[7];
+    smp.active = act;
+}
+
+// Visits every lattice sample of a ray that lies in an occupied macroblock
+// and passes the cell-mask pre-test, in order.  For each one f(k, id, p, fr)
+// is called with the atlas block id, padded cell and 16-bit fractions; f
+// returns true to stop the march.  Per-block and per-sample hooks feed the
+// visit trace.  Returns the k at which f stopped the march, or -1.
+template <typename OnBlock, typename OnInBlock, typename OnSample>
+__host__ __device__ __forceinline__ int64_t march_ray(const GridArgs& g, const int64_t o[3], const int32_t s[3],
+                                             OnBlock&& on_block, OnInBlock&& on_inblock,
+                                             OnSample&& on_sample) {
+    const int bs = 16 + g.logB;
+    const int64_t L = int64_t(g.N) << 16;
+    int64_t klo, khi;
+    if (!entry_range(o, s, L, klo, khi)) return -1;
+    float inv[3];
+    int32_t P[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        inv[a] = s[a] != 0 ? 1.0f / float(s[a] < 0 ? -s[a] : s[a]) : 0.0f;
+        P[a] = int32_t(o[a] + klo * int64_t(s[a]));  // inside [0, N 2^16)
+    }
+    int64_t k = klo;
+    while (k <= khi) {
+        int32_t b[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) b[a] = P[a] >> bs;
+        // Guards: the exact integer arithmetic above keeps P inside the grid
+        // and every sample of [k, kn) inside block b; these checks make any
+        // violation end the ray instead of indexing outside the buffers.
+        if ((unsigned)b[0] >= (unsigned)g.G || (unsigned)b[1] >= (unsigned)g.G || (unsigned)b[2] >= (unsigned)g.G)
+            return -1;
+        int32_t nstep = block_steps(P, s, inv, b, bs);
+        while (nstep > 1 && (((P[0] + (nstep - 1) * s[0]) >> bs) != b[0] ||
+                             ((P[1] + (nstep - 1) * s[1]) >> bs) != b[1] ||
+                             ((P[2] + (nstep - 1) * s[2]) >> bs) != b[2]))
+            --nstep;
+        const int64_t kn = (k + int64_t(nstep)) < (khi + 1) ? (k + int64_t(nstep)) : (khi + 1);
+        const int32_t lin = (b[2] * g.G + b[1]) * g.G + b[0];
+        const int32_t id = g.ind[lin];
+        const bool occ = (id >= 0) && (id < g.n_blocks);
+        on_block(lin, occ);
+        if (occ) {
+            const uint32_t* __restrict__ mk = g.mask + int64_t(id) * g.mask_words;
+            int32_t q[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) q[a] = P[a] - (b[a] << bs) + 32768;  // padded Q16 coordinate
+            for (int64_t kk = k; kk < kn; ++kk) {
+                const int32_t p[3] = {q[0] >> 16, q[1] >> 16, q[2] >> 16};
+                const int32_t cell = (p[2] * g.Bc + p[1]) * g.Bc + p[0];
+                on_inblock();
+                if ((mk[cell >> 5] >> (cell & 31)) & 1u) {
+                    const int32_t fr[3] = {q[0] & 0xFFFF, q[1] & 0xFFFF, q[2] & 0xFFFF};
+                    if (on_sample(kk, id, p, fr)) return kk;
+                }
+#pragma unroll
+                for (int a = 0; a < 3; ++a) q[a] += s[a];
+            }
+        }
+        const int32_t adv = int32_t(kn - k);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) P[a] += adv * s[a];  // |adv s| <= B 2^16 + |s|
+        k = kn;
+    }
+    return -1;
+}
+
+}  // namespace snerg

@@ -1,0 +1,156 @@
+// Deferred shading MLP (Eq. 7, Section 4.2): x = [C_d, V, d, PE(d)] (34),
+// two ReLU layers of 16 channels, sigmoid output (3).  Weights are the
+// 883-float vector W1[16][34] b1 W2[16][16] b2 W3[3][16] b3 ([out][in]).
+//
+//  - mlp_forward_f32: one ray per lane, FP32 FMAs; wave-uniform weight
+//    addresses become scalar loads.
+//  - mlp_forward_f16_wave: the 64 rays of a wavefront as MFMA tiles
+//    (v_mfma_f32_16x16x16_f16, FP16 operands, FP32 accumulation), computing
+//    H^T = W X^T with hidden units as rows and 16 rays per column tile.  x
+//    is moved into the B-operand layout through LDS; each layer's FP32
+//    result, after bias and ReLU, is already in the next layer's B-operand
+//    layout.  Sigmoid stays FP32.
+#pragma once
+
+#include "snerg_dev.h"
+
+namespace snerg {
+
+__device__ __forceinline__ void encode_x(const float C[3], const float V[4], const float d[3],
+                                         float x[kMlpIn]) {
+    x[0] = C[0]; x[1] = C[1]; x[2] = C[2];
+    x[3] = V[0]; x[4] = V[1]; x[5] = V[2]; x[6] = V[3];
+    x[7] = d[0]; x[8] = d[1]; x[9] = d[2];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        const float sc = float(1 << l);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float sn, cn;
+            sincospif(sc * d[a], &sn, &cn);  // sin(2^l pi d), cos(2^l pi d)
+            x[10 + 6 * l + a] = sn;
+            x[13 + 6 * l + a] = cn;
+        }
+    }
+}
+
+__device__ __forceinline__ float sigmoid_f32(float z) { return 1.0f / (1.0f + __expf(-z)); }
+
+__device__ __forceinline__ void mlp_forward_f32(const float* __restrict__ W, const float C[3],
+                                                const float V[4], const float d[3], float R[3]) {
+    float x[kMlpIn];
+    encode_x(C, V, d, x);
+    float h1[kMlpH], h2[kMlpH];
+#pragma unroll
+    for (int j = 0; j < kMlpH; ++j) {
+        float s = W[kOffB1 + j];
+#pragma unroll
+        for (int i = 0; i < kMlpIn; ++i) s = fmaf(W[kOffW1 + j * kMlpIn + i], x[i], s);
+        h1[j] = fmaxf(s, 0.0f);
+    }
+#pragma unroll
+    for (int j = 0; j < kMlpH; ++j) {
+        float s = W[kOffB2 + j];
+#pragma unroll
+        for (int i = 0; i < kMlpH; ++i) s = fmaf(W[kOffW2 + j * kMlpH + i], h1[i], s);
+        h2[j] = fmaxf(s, 0.0f);
+    }
+#pragma unroll
+    for (int j = 0; j < kMlpOut; ++j) {
+        float s = W[kOffB3 + j];
+#pragma unroll
+        for (int i = 0; i < kMlpH; ++i) s = fmaf(W[kOffW3 + j * kMlpH + i], h2[i], s);
+        R[j] = sigmoid_f32(s);
+    }
+}
+
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kXPad = 48;              // 34 inputs padded to 3 K-chunks of 16
+constexpr int kXRow = kXPad + 8;       // LDS row stride in halves (breaks bank alignment)
+constexpr int kMaxWavesF16 = 4;
+
+// A-operand fragment of a row-major [rows][cols] FP32 matrix for a 16x16 tile
+// (rows r0.., cols c0..): lane l holds M[r0 + l%16][c0 + 4(l/16) + j], zero
+// outside [rows, cols).
+__device__ __forceinline__ half4_t a_frag(const float* __restrict__ M, int rows, int cols, int r0, int c0,
+                                          int lane) {
+    const int r = r0 + (lane & 15);
+    const int c = c0 + 4 * (lane >> 4);
+    half4_t v;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = (r < rows && c + j < cols) ? _Float16(M[r * cols + c + j]) : _Float16(0.0f);
+    return v;
+}
+
+// Accumulator initialised with a bias: lane l holds rows 4(l/16) + v.
+__device__ __forceinline__ float4_t bias_frag(const float* __restrict__ b, int rows, int lane) {
+    float4_t v;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int r = 4 * (lane >> 4) + j;
+        v[j] = r < rows ? b[r] : 0.0f;
+    }
+    return v;
+}
+
+__device__ __forceinline__ half4_t relu_to_half(float4_t v) {
+    half4_t h;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) h[j] = _Float16(fmaxf(v[j], 0.0f));
+    return h;
+}
+
+// All 64 lanes of the wavefront must call this together.  Lanes with
+// use == false get R = 0 (their inputs still flow through the tiles).
+__device__ __forceinline__ void mlp_forward_f16_wave(const float* __restrict__ W, bool use, const float C[3],
+                                                     const float V[4], const float d[3], float R[3]) {
+    __shared__ _Float16 xs[kMaxWavesF16][64][kXRow];
+    const int lane = threadIdx.x & 63;
+    const int wave = (threadIdx.x >> 6) & (kMaxWavesF16 - 1);
+    float x[kMlpIn];
+    encode_x(C, V, d, x);
+#pragma unroll
+    for (int i = 0; i < kXPad; ++i) xs[wave][lane][i] = _Float16(i < kMlpIn ? x[i] : 0.0f);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    half4_t w1[3];
+#pragma unroll
+    for (int kc = 0; kc < 3; ++kc) w1[kc] = a_frag(W + kOffW1, kMlpH, kMlpIn, 0, 16 * kc, lane);
+    const half4_t w2 = a_frag(W + kOffW2, kMlpH, kMlpH, 0, 0, lane);
+    const half4_t w3 = a_frag(W + kOffW3, kMlpOut, kMlpH, 0, 0, lane);
+    const float4_t bb1 = bias_frag(W + kOffB1, kMlpH, lane);
+    const float4_t bb2 = bias_frag(W + kOffB2, kMlpH, lane);
+    const float4_t bb3 = bias_frag(W + kOffB3, kMlpOut, lane);
+
+    float4_t out[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        // B operand of layer 1: lane l holds x_{16g + l%16}[16kc + 4(l/16) + v]
+        const _Float16* row = &xs[wave][16 * g + (lane & 15)][4 * (lane >> 4)];
+        float4_t acc = bb1;
+#pragma unroll
+        for (int kc = 0; kc < 3; ++kc) {
+            const half4_t xb = *reinterpret_cast<const half4_t*>(row + 16 * kc);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16f16(w1[kc], xb, acc, 0, 0, 0);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16f16(w2, relu_to_half(acc), bb2, 0, 0, 0);
+        out[g] = __builtin_amdgcn_mfma_f32_16x16x16f16(w3, relu_to_half(acc), bb3, 0, 0, 0);
+    }
+    // Output row i (0..2) of ray 16g + n sits in lane n, element i, of out[g].
+    const int src = lane & 15;
+    const int my_g = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < kMlpOut; ++i) {
+        float v0 = __shfl(out[0][i], src), v1 = __shfl(out[1][i], src);
+        float v2 = __shfl(out[2][i], src), v3 = __shfl(out[3][i], src);
+        float z = my_g == 0 ? v0 : (my_g == 1 ? v1 : (my_g == 2 ? v2 : v3));
+        R[i] = use ? sigmoid_f32(z) : 0.0f;
+    }
+    __builtin_amdgcn_wave_barrier();  // xs is rewritten by the next call
+}
+
+}  // namespace snerg

@@ -1,0 +1,218 @@
+// Forward kernels: march + composite + deferred MLP (Section 5.2, Eq. 5-7),
+// and the visit-trace kernel.
+#include "march.h"
+#include "mlp.h"
+#include "snerg_launch.h"
+
+namespace snerg {
+
+struct RayAccum {
+    float C[3], V[4], T;
+    bool gate;
+};
+
+// Composites one active sample (Eq. 2, 5, 6); kx = sigma_scale * delta / value scale.
+__device__ __forceinline__ void composite(RayAccum& st, const Sample& smp, float kx, float cs) {
+    const float x = smp.sigma_raw * kx;
+    const float e = __expf(-x);
+    const float alpha = 1.0f - e;
+    const float w = st.T * alpha;
+    const float wc = w * cs;
+    st.C[0] += wc * smp.rgb[0];
+    st.C[1] += wc * smp.rgb[1];
+    st.C[2] += wc * smp.rgb[2];
+    st.V[0] += wc * smp.feat[0];
+    st.V[1] += wc * smp.feat[1];
+    st.V[2] += wc * smp.feat[2];
+    st.V[3] += wc * smp.feat[3];
+    st.T *= e;
+    st.gate = true;
+}
+
+template <int VT>
+__device__ __forceinline__ void march_composite(const RenderArgs& a, const int64_t o[3], const int32_t s[3],
+                                                RayAccum& st) {
+    const GridArgs& g = a.grid;
+    const float cs = VT == 0 ? (1.0f / 255.0f) : 1.0f;
+    const float kx = g.sigma_scale * cs / float(g.N);
+    const float t_stop = a.opts.t_stop;
+    const bool early = a.opts.early_stop != 0;
+    march_ray(
+        g, o, s, [](int32_t, bool) {}, []() {},
+        [&](int64_t, int32_t id, const int32_t p[3], const int32_t fr[3]) {
+            Sample smp;
+            const uint8_t* blk = g.vox + int64_t(id) * g.vox_stride;
+            if (VT == 0) gather_u8(blk, g.Bp, p, fr, smp); else gather_f32(blk, g.Bp, p, fr, smp);
+            if (!smp.active) return false;
+            composite(st, smp, kx, cs);
+            return early && st.T < t_stop;
+        });
+}
+
+// Pixel of lane `lane` in wavefront tile t; false when the tile overhangs the image.
+__device__ __forceinline__ bool tile_pixel(const RenderArgs& a, int64_t t, int lane, int& ci, int& px,
+                                           int& py, int64_t& rid) {
+    ci = find_camera_by_tile(a.cams, a.n_cams, t);
+    const DevCamera& c = a.cams[ci];
+    const int64_t tl = t - c.tile_offset;
+    const int tx = int(tl % c.tiles_x), ty = int(tl / c.tiles_x);
+    px = tx * a.tile_w + (lane % a.tile_w);
+    py = ty * a.tile_h + (lane / a.tile_w);
+    rid = c.ray_offset + int64_t(py) * c.W + px;
+    return px < c.W && py < c.H;
+}
+
+template <int VT, int MLP>
+__device__ __forceinline__ void render_ray(const RenderArgs& a, bool valid, int ci, int px, int py,
+                                           int64_t out_idx) {
+    RayAccum st = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, 1.0f, false};
+    float d[3] = {0.f, 0.f, 1.f};
+    if (valid) {
+        int64_t o[3];
+        int32_t s[3];
+        ray_setup(a.cams[ci], a.grid.N, px, py, o, s, d);
+        march_composite<VT>(a, o, s, st);
+    }
+    float R[3] = {0.f, 0.f, 0.f};
+    const bool use_mlp = valid && st.gate && a.opts.mlp_on;
+    if (MLP == kMlpF32) {
+        if (use_mlp) mlp_forward_f32(a.mlp, st.C, st.V, d, R);
+    } else if (MLP == kMlpF16) {
+        mlp_forward_f16_wave(a.mlp, use_mlp, st.C, st.V, d, R);
+    }
+    if (valid) {
+        float4 out;
+        out.x = st.C[0] + st.T * a.opts.bg[0] + R[0];
+        out.y = st.C[1] + st.T * a.opts.bg[1] + R[1];
+        out.z = st.C[2] + st.T * a.opts.bg[2] + R[2];
+        out.w = 1.0f - st.T;
+        reinterpret_cast<float4*>(a.out)[out_idx] = out;
+        if (a.aux) {
+            float4* ax = reinterpret_cast<float4*>(a.aux) + 2 * out_idx;
+            ax[0] = make_float4(st.C[0], st.C[1], st.C[2], st.V[0]);
+            ax[1] = make_float4(st.V[1], st.V[2], st.V[3], st.gate ? st.T : -1.0f);
+        }
+    }
+}
+
+template <int VT, int MLP>
+__global__ __launch_bounds__(256) void k_render(RenderArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wpg = blockDim.x >> 6;
+    if (a.mode == kModeList) {
+        const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+        const bool valid = i < a.n_rays;
+        int ci = 0, px = 0, py = 0;
+        if (valid) {
+            const int64_t r = a.ray_ids[i];
+            ci = find_camera_by_ray(a.cams, a.n_cams, r);
+            const int64_t local = r - a.cams[ci].ray_offset;
+            py = int(local / a.cams[ci].W);
+            px = int(local - int64_t(py) * a.cams[ci].W);
+        }
+        render_ray<VT, MLP>(a, valid, ci, px, py, i);
+    } else if (a.mode == kModeTiles) {
+        const int64_t t = int64_t(blockIdx.x) * wpg + wave;
+        if (t >= a.total_tiles) return;  // wave-uniform
+        int ci, px, py;
+        int64_t rid;
+        const bool valid = tile_pixel(a, t, lane, ci, px, py, rid);
+        render_ray<VT, MLP>(a, valid, ci, px, py, rid);
+    } else {
+        for (;;) {
+            int64_t t = 0;
+            if (lane == 0) t = atomicAdd(a.tile_counter, 1);
+            t = __shfl(t, 0);
+            if (t >= a.total_tiles) break;  // wave-uniform; every wave reaches it
+            int ci, px, py;
+            int64_t rid;
+            const bool valid = tile_pixel(a, t, lane, ci, px, py, rid);
+            render_ray<VT, MLP>(a, valid, ci, px, py, rid);
+        }
+    }
+}
+
+// Visit trace: one lane per listed ray (or per ray id when the list is absent).
+template <int VT>
+__global__ __launch_bounds__(256) void k_trace(RenderArgs a) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= a.n_rays) return;
+    const int64_t r = a.ray_ids ? a.ray_ids[i] : i;
+    const int ci = find_camera_by_ray(a.cams, a.n_cams, r);
+    const DevCamera& c = a.cams[ci];
+    const int64_t local = r - c.ray_offset;
+    const int py = int(local / c.W), px = int(local - int64_t(py) * c.W);
+    int64_t o[3];
+    int32_t s[3];
+    float d[3];
+    ray_setup(c, a.grid.N, px, py, o, s, d);
+    const GridArgs& g = a.grid;
+    const float cs = VT == 0 ? (1.0f / 255.0f) : 1.0f;
+    const float kx = g.sigma_scale * cs / float(g.N);
+    RayAccum st = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, 1.0f, false};
+    int32_t n_trav = 0, n_occ = 0, n_in = 0, n_act = 0;
+    int32_t* vis = a.visits ? a.visits + i * a.max_visits : nullptr;
+    const int64_t stop = march_ray(
+        g, o, s,
+        [&](int32_t lin, bool occ) {
+            ++n_trav;
+            if (occ) {
+                if (vis && n_occ < a.max_visits) vis[n_occ] = lin;
+                ++n_occ;
+            }
+        },
+        [&]() { ++n_in; },
+        [&](int64_t, int32_t id, const int32_t p[3], const int32_t fr[3]) {
+            Sample smp;
+            const uint8_t* blk = g.vox + int64_t(id) * g.vox_stride;
+            if (VT == 0) gather_u8(blk, g.Bp, p, fr, smp); else gather_f32(blk, g.Bp, p, fr, smp);
+            if (!smp.active) return false;
+            ++n_act;
+            composite(st, smp, kx, cs);
+            return a.opts.early_stop && st.T < a.opts.t_stop;
+        });
+    a.counts[i] = n_occ;
+    if (a.counters) {
+        int32_t* cn = a.counters + 5 * i;
+        cn[0] = n_trav;
+        cn[1] = n_occ;
+        cn[2] = n_in;
+        cn[3] = n_act;
+        cn[4] = int32_t(stop);
+    }
+}
+
+template <int VT, int MLP>
+static hipError_t launch_render_t(const RenderArgs& a, int wpg, int n_groups, hipStream_t s) {
+    const int threads = 64 * wpg;
+    unsigned blocks;
+    if (a.mode == kModeList) blocks = unsigned((a.n_rays + threads - 1) / threads);
+    else if (a.mode == kModeTiles) blocks = unsigned((a.total_tiles + wpg - 1) / wpg);
+    else blocks = unsigned(n_groups);
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_render<VT, MLP>), dim3(blocks), dim3(threads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_render(const RenderArgs& a, int vt, int mlp_mode, int wpg, int n_groups,
+                         hipStream_t s) {
+    if (vt == 0) {
+        if (mlp_mode == kMlpF16) return launch_render_t<0, kMlpF16>(a, wpg, n_groups, s);
+        if (mlp_mode == kMlpF32) return launch_render_t<0, kMlpF32>(a, wpg, n_groups, s);
+        return launch_render_t<0, kMlpOff>(a, wpg, n_groups, s);
+    }
+    if (mlp_mode == kMlpF16) return launch_render_t<1, kMlpF16>(a, wpg, n_groups, s);
+    if (mlp_mode == kMlpF32) return launch_render_t<1, kMlpF32>(a, wpg, n_groups, s);
+    return launch_render_t<1, kMlpOff>(a, wpg, n_groups, s);
+}
+
+hipError_t launch_trace(const RenderArgs& a, int vt, hipStream_t s) {
+    if (a.n_rays <= 0) return hipSuccess;
+    const unsigned blocks = unsigned((a.n_rays + 255) / 256);
+    if (vt == 0) hipLaunchKernelGGL(k_trace<0>, dim3(blocks), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_trace<1>, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace snerg

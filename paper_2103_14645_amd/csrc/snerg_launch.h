@@ -1,0 +1,71 @@
+// Host-side interface between the C ABI (api.cpp) and the HIP kernels.
+#pragma once
+
+#include "snerg_dev.h"
+
+namespace snerg {
+
+enum LaunchMode : int32_t {
+    kModeTiles = 0,       // one wavefront per 64-pixel tile, one launch
+    kModePersistent = 1,  // resident workgroups pull tiles from a global counter
+    kModeList = 2,        // one lane per entry of a ray-id list
+};
+
+enum MlpMode : int32_t {
+    kMlpOff = 0,
+    kMlpF32 = 1,   // FP32 per lane
+    kMlpF16 = 2,   // FP16 MFMA tiles, FP32 accumulation
+};
+
+struct RenderArgs {
+    GridArgs grid;
+    RenderOpts opts;
+    const float* mlp;
+    const DevCamera* cams;
+    int32_t n_cams;
+    int32_t mode;
+    const int64_t* ray_ids;
+    int64_t n_rays;
+    int64_t total_tiles;
+    int32_t tile_w, tile_h;  // tile_w * tile_h == 64
+    int32_t* tile_counter;   // persistent mode
+    float* out;              // [n][4]
+    float* aux;              // [n][8] or null
+    // visit tracing
+    int32_t* visits;
+    int32_t max_visits;
+    int32_t* counts;
+    int32_t* counters;
+};
+
+struct BackwardArgs {
+    GridArgs grid;
+    RenderOpts opts;
+    const float* mlp;
+    const DevCamera* cams;
+    int32_t n_cams;
+    int32_t mlp_mode;
+    const int64_t* ray_ids;
+    int64_t n_rays;
+    const float* aux;
+    const float* grad_rgba;
+    float* g_mlp_partial;  // [n_groups][883]
+    float* grad_dens;
+    float* grad_rgb;
+    float* grad_feat;
+};
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
+hipError_t launch_pack(const PackedLayout& L, int32_t n_blocks, bool f32, const int32_t* ind,
+                       const void* dens, const void* rgb, const void* feat, uint8_t* packed,
+                       hipStream_t s);
+
+// vt: 0 = uint8 grid, 1 = float32 grid.
+hipError_t launch_render(const RenderArgs& a, int vt, int mlp_mode, int waves_per_group,
+                         int n_groups, hipStream_t s);
+hipError_t launch_trace(const RenderArgs& a, int vt, hipStream_t s);
+hipError_t launch_backward(const BackwardArgs& a, int n_groups, hipStream_t s);
+hipError_t launch_reduce_mlp(const float* partial, int n_groups, float* out, hipStream_t s);
+
+}  // namespace snerg

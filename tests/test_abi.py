@@ -1,0 +1,154 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/snerg.h, and its host-only validation returns the
+documented status for each bad argument before touching the device (a NULL
+handle is passed, so any call that got past validation would fail with
+"handle is NULL" instead)."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2103_14645_amd import snerg as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = ctypes.c_void_p(0x10000)  # never dereferenced: validation is host-only
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "snerg.h")).read()
+    return sorted(set(re.findall(r"\b(snerg_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_entry_point():
+    lib = S.lib()
+    names = declared_functions()
+    assert {"snerg_render", "snerg_render_backward", "snerg_pack_grid", "snerg_trace_visits"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(S.EXPORTED) == set(names)
+
+
+def test_status_strings():
+    lib = S.lib()
+    for code in (0, -1, -2, -3, -4, -5):
+        assert lib.snerg_status_string(code)
+    assert lib.snerg_status_string(-99) == b"unknown status"
+
+
+def test_packed_size_layout_and_errors():
+    # block_lin (256-aligned) + mask ((B+1)^3 bits per block, 256-aligned) + (B+2)^3 voxels
+    n = 433
+    words = math.ceil(33 ** 3 / 32)
+    expect = ((n * 4 + 255) // 256) * 256 + (((n * words * 4) + 255) // 256) * 256 + n * 34 ** 3 * 8
+    assert S.snerg_packed_size(512, 32, n, S.SNERG_U8) == expect
+    assert S.snerg_packed_size(512, 32, n, S.SNERG_F32) == expect + n * 34 ** 3 * 24
+    for args, code in [((512, 24, 1, 0), S.SNERG_ERR_UNSUPPORTED), ((500, 32, 1, 0), S.SNERG_ERR_UNSUPPORTED),
+                       ((32768, 32, 1, 0), S.SNERG_ERR_RANGE), ((512, 32, 1, 7), S.SNERG_ERR_UNSUPPORTED),
+                       ((512, 32, -1, 0), S.SNERG_ERR_INVALID_ARG),
+                       ((64, 8, 513, 0), S.SNERG_ERR_INVALID_ARG)]:
+        with pytest.raises(S.SnergError) as e:
+            S.snerg_packed_size(*args)
+        assert e.value.code == code
+
+
+class NullHandle:
+    h = None
+
+
+def good_camera():
+    c = S.snerg_camera()
+    c.eye[:] = [0.0, 0.0, -2.0]
+    c.fwd[:] = [0.0, 0.0, 1.0]
+    c.right[:] = [1.0, 0.0, 0.0]
+    c.up[:] = [0.0, 1.0, 0.0]
+    c.W, c.H, c.focal = 8, 4, 10.0
+    return c
+
+
+def call_render(grid=None, cams=None, n_cams=1, ray_ids=None, n_rays=32, opts=None, mlp=FAKE, out=FAKE):
+    lib = S.lib()
+    grid = grid or S.snerg_grid(64, 8, 8, S.SNERG_U8, FAKE.value, FAKE.value, 50.0, 0)
+    if cams is None:
+        cams = (S.snerg_camera * 1)(good_camera())
+    opts = opts or S.make_opts()
+    return lib.snerg_render(None, ctypes.byref(grid), mlp, cams, n_cams, ray_ids, n_rays, ctypes.byref(opts),
+                            out, None, None)
+
+
+def last_error():
+    return S.lib().snerg_last_error().decode()
+
+
+def test_render_validation_paths():
+    assert call_render() == S.SNERG_ERR_INVALID_ARG and "handle" in last_error()   # all valid, no handle
+    assert call_render(grid=S.snerg_grid(64, 6, 8, 0, FAKE.value, FAKE.value, 50.0, 0)) == S.SNERG_ERR_UNSUPPORTED
+    assert call_render(grid=S.snerg_grid(64, 8, 8, 0, None, FAKE.value, 50.0, 0)) == S.SNERG_ERR_INVALID_ARG
+    assert call_render(grid=S.snerg_grid(64, 8, 8, 0, FAKE.value, None, 50.0, 0)) == S.SNERG_ERR_INVALID_ARG
+    assert call_render(grid=S.snerg_grid(64, 8, 8, 0, FAKE.value, FAKE.value, float("nan"), 0)) == -1
+    assert call_render(n_rays=31) == S.SNERG_ERR_INVALID_ARG          # must equal W*H without ray_ids
+    assert call_render(n_rays=-1) == S.SNERG_ERR_INVALID_ARG
+    assert call_render(n_cams=0) == S.SNERG_ERR_INVALID_ARG
+    assert call_render(mlp=None) == S.SNERG_ERR_INVALID_ARG and "mlp" in last_error()
+    assert call_render(mlp=None, opts=S.make_opts(mlp_on=False)) == S.SNERG_ERR_INVALID_ARG  # handle again
+    assert "handle" in last_error()
+    assert call_render(out=None) == S.SNERG_ERR_INVALID_ARG
+    o = S.make_opts(); o.flags = 1 << 9
+    assert call_render(opts=o) == S.SNERG_ERR_UNSUPPORTED
+    o = S.make_opts(); o.t_stop = float("inf")
+    assert call_render(opts=o) == S.SNERG_ERR_INVALID_ARG
+    o = S.make_opts(); o.bg[1] = float("nan")
+    assert call_render(opts=o) == S.SNERG_ERR_INVALID_ARG
+    assert call_render(ray_ids=FAKE, n_rays=5) == S.SNERG_ERR_INVALID_ARG and "handle" in last_error()
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("W", 0, S.SNERG_ERR_INVALID_ARG), ("focal", 0.0, S.SNERG_ERR_INVALID_ARG),
+    ("focal", float("nan"), S.SNERG_ERR_INVALID_ARG), ("eye", [float("inf"), 0, 0], S.SNERG_ERR_INVALID_ARG),
+    ("eye", [0.0, 0.0, 1500.0], S.SNERG_ERR_RANGE), ("fwd", [0.0, 0.1, 1.0], S.SNERG_ERR_INVALID_ARG),
+    ("up", [1.0, 0.0, 0.0], S.SNERG_ERR_INVALID_ARG),
+])
+def test_camera_validation(field, value, code):
+    c = good_camera()
+    setattr(c, field, (ctypes.c_double * 3)(*value)) if isinstance(value, list) else setattr(c, field, value)
+    cams = (S.snerg_camera * 1)(c)
+    n = max(c.W, 0) * c.H
+    assert call_render(cams=cams, n_rays=n) == code
+
+
+def test_backward_trace_pack_autotune_validation():
+    lib = S.lib()
+    cams = (S.snerg_camera * 1)(good_camera())
+    opts = S.make_opts()
+    u8 = S.snerg_grid(64, 8, 8, S.SNERG_U8, FAKE.value, FAKE.value, 50.0, 0)
+    f32 = S.snerg_grid(64, 8, 8, S.SNERG_F32, FAKE.value, FAKE.value, 50.0, 0)
+    bw = lambda g, o=opts, gm=FAKE: lib.snerg_render_backward(None, ctypes.byref(g), FAKE, cams, 1, None, 32,
+                                                              ctypes.byref(o), FAKE, FAKE, gm, FAKE, FAKE, FAKE,
+                                                              None)
+    assert bw(u8) == S.SNERG_ERR_UNSUPPORTED
+    assert bw(f32, gm=None) == S.SNERG_ERR_INVALID_ARG
+    assert bw(f32) == S.SNERG_ERR_INVALID_ARG and "handle" in last_error()
+    assert bw(f32, o=S.make_opts(fp16=True)) == S.SNERG_ERR_UNSUPPORTED
+    tr = lambda mv, vis: lib.snerg_trace_visits(None, ctypes.byref(u8), cams, 1, None, 32, ctypes.byref(opts),
+                                                mv, vis, FAKE, None, None)
+    assert tr(-1, FAKE) == S.SNERG_ERR_INVALID_ARG
+    assert tr(4, None) == S.SNERG_ERR_INVALID_ARG
+    assert tr(0, None) == S.SNERG_ERR_INVALID_ARG and "handle" in last_error()
+    pk = lambda nbytes: lib.snerg_pack_grid(None, 64, 8, 8, 0, FAKE, FAKE, FAKE, FAKE, FAKE, nbytes, None)
+    assert pk(10) == S.SNERG_ERR_WORKSPACE
+    assert pk(1 << 30) == S.SNERG_ERR_INVALID_ARG and "handle" in last_error()
+    bad = (S.snerg_tuning * 1)(S.snerg_tuning(8, 4, 4, 8))
+    at = lambda cand, n, reps: lib.snerg_autotune(None, ctypes.byref(u8), FAKE, cams, 1, ctypes.byref(opts), cand,
+                                                  n, reps, FAKE, None, None, None)
+    assert at(bad, 1, 3) == S.SNERG_ERR_INVALID_ARG and "64" in last_error()
+    assert at(None, 0, 0) == S.SNERG_ERR_INVALID_ARG
+    assert at(None, 0, 3) == S.SNERG_ERR_INVALID_ARG and "handle" in last_error()
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(S, "_lib", None)
+    monkeypatch.setattr(S, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        S.lib()

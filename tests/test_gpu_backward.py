@@ -1,0 +1,100 @@
+"""GPU adjoint against the FP64 oracle's gradient (which is itself pinned to
+central differences).  Bar: |g_gpu - g_oracle| <= 1e-4 * max|g_oracle| + 1e-7
+per element, for the MLP parameters and every grid value."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from paper_2103_14645_amd import autograd as A
+from paper_2103_14645_amd import snerg as S
+from tests.gpu_helpers import handle, say
+
+pytestmark = pytest.mark.gpu
+
+
+def shadow_values(g, seed):
+    rng = np.random.default_rng(seed)
+    d = g.dens / 255.0
+    return (np.where(d > 0, d + 0.01 * rng.uniform(-1, 1, d.shape), 0.0).astype(np.float32),
+            (g.rgb / 255.0 + 0.01 * rng.uniform(-1, 1, g.rgb.shape)).astype(np.float32),
+            (g.feat / 255.0 + 0.01 * rng.uniform(-1, 1, g.feat.shape)).astype(np.float32))
+
+
+def run_backward(g, vals, mlp, cams, g_rgba, ids=None, **kw):
+    h = handle()
+    r = A.ShadowRenderer(h, g.N, g.B, g.indirection, g.n_blocks)
+    dens, rgb, feat = (torch.from_numpy(v).cuda() for v in vals)
+    m = S.mlp_tensor(mlp)
+    cams_c = S.make_cameras(cams)
+    opts = S.make_opts(**kw)
+    idt = torch.from_numpy(np.asarray(ids, np.int64)).cuda() if ids is not None else None
+    dens.requires_grad_(True); rgb.requires_grad_(True); feat.requires_grad_(True); m.requires_grad_(True)
+    out = A.render_shadow(r, dens, rgb, feat, m, cams_c, idt, opts)
+    out.backward(torch.from_numpy(g_rgba.astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    return (m.grad.cpu().numpy().astype(np.float64), dens.grad.cpu().numpy(), rgb.grad.cpu().numpy(),
+            feat.grad.cpu().numpy(), out.detach().cpu().numpy())
+
+
+def compare(name, gpu, ref):
+    scale = float(np.abs(ref).max())
+    err = float(np.abs(gpu - ref).max())
+    say(f"  {name}: max|ref|={scale:.3e} max_err={err:.3e}")
+    assert err <= 1e-4 * scale + 1e-7, name
+
+
+@pytest.mark.parametrize("n_occ,seed,early,mlp_on,subset", [(96, 4, False, True, False), (200, 2, True, True, False),
+                                                           (120, 5, True, False, False), (200, 7, True, True, True)])
+def test_backward_matches_oracle_gradient(n_occ, seed, early, mlp_on, subset):
+    say(f"backward n_occ={n_occ} seed={seed} early={early} mlp={mlp_on} subset={subset}")
+    g = W.tiny_grid(n_occupied=n_occ, seed=seed)
+    vals = shadow_values(g, seed)
+    mlp = W.mlp_weights(seed + 1)
+    cams = [W.orbit_camera(48, 40, seed=seed + 2), W.orbit_camera(21, 35, seed=seed + 3)]
+    n = sum(c.n_rays for c in cams)
+    rng = np.random.default_rng(seed)
+    ids = np.sort(rng.choice(n, n // 2, replace=False)) if subset else None
+    m = len(ids) if subset else n
+    g_rgba = rng.normal(size=(m, 4)) / m
+    gm, gd, gr, gf, out = run_backward(g, vals, mlp, cams, g_rgba, ids=ids, early_stop=early, mlp_on=mlp_on)
+    og = O.OracleGrid(g, values=vals)
+    # near-threshold stops could pick a different branch: require none here
+    alt = [O.render(og, mlp, cams, ray_ids=ids, early_stop=early, mlp_on=mlp_on, t_stop=1e-3 * f)["counters"]
+           for f in (1 - 1e-5, 1 + 1e-5)]
+    assert np.array_equal(alt[0], alt[1])
+    om, od, orr, of = O.render_grad(og, mlp, cams, g_rgba, ray_ids=ids, early_stop=early, mlp_on=mlp_on)
+    compare("mlp", gm, om)
+    compare("dens", gd, od)
+    compare("rgb", gr, orr)
+    compare("feat", gf, of)
+    ref = O.render(og, mlp, cams, ray_ids=ids, early_stop=early, mlp_on=mlp_on)["rgba"]
+    assert np.abs(out - ref).max() <= 1e-4
+
+
+def test_mse_step_reduces_loss():
+    say("autograd: one SGD step on an MSE against perturbed targets lowers the loss")
+    g = W.tiny_grid(n_occupied=96, seed=4)
+    vals = shadow_values(g, 4)
+    mlp = W.mlp_weights(5)
+    cams = [W.orbit_camera(32, 32, seed=6)]
+    target_mlp, _ = W.perturbed(mlp, g, seed=3)
+    h = handle()
+    r = A.ShadowRenderer(h, g.N, g.B, g.indirection, g.n_blocks)
+    dens, rgb, feat = (torch.from_numpy(v).cuda() for v in vals)
+    cams_c = S.make_cameras(cams)
+    with torch.no_grad():
+        target = A.render_shadow(r, dens, rgb, feat, S.mlp_tensor(target_mlp), cams_c)
+    m = S.mlp_tensor(mlp).requires_grad_(True)
+    losses = []
+    for _ in range(3):
+        out = A.render_shadow(r, dens, rgb, feat, m, cams_c)
+        loss = ((out[:, :3] - target[:, :3]) ** 2).mean()
+        losses.append(float(loss))
+        m.grad = None
+        loss.backward()
+        with torch.no_grad():
+            m -= 0.5 * m.grad / (m.grad.norm() + 1e-12) * 0.05
+    say(f"  losses {losses}")
+    assert losses[-1] < losses[0]

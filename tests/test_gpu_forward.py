@@ -1,0 +1,178 @@
+"""GPU parity of the forward render and the visit trace against the FP64 oracle.
+
+Bars: visit lists, counts and per-ray counters bit-exact; FP32 RGBA within
+1e-4 absolute; the FP16-MFMA MLP path within 2e-3 absolute.  Rays whose
+early-stop decision lies within a relative 1e-5 of t_stop may match either
+oracle branch.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from paper_2103_14645_amd import snerg as S
+from tests.gpu_helpers import device_grid, gpu_render, handle, oracle_variants, parity_error, say
+
+pytestmark = pytest.mark.gpu
+
+TOL_F32 = 1e-4
+TOL_F16 = 2e-3
+
+
+def tiny_case(n_occ, seed):
+    g = W.tiny_grid(n_occupied=n_occ, seed=seed)
+    cams = [W.orbit_camera(64, 64, seed=seed + 1), W.orbit_camera(37, 23, seed=seed + 2),
+            W.look_at((0.3, -1.7, 0.9), 19, 41, 53.0)]
+    return g, cams, W.mlp_weights(seed + 2)
+
+
+@pytest.mark.parametrize("n_occ,seed,early,mlp_on", [(8, 0, True, True), (64, 1, True, True),
+                                                     (200, 2, True, True), (200, 3, False, True),
+                                                     (120, 4, True, False)])
+def test_tiny_all_rays_fp32(n_occ, seed, early, mlp_on):
+    say(f"tiny fp32 n_occ={n_occ} seed={seed} early={early} mlp={mlp_on}")
+    g, cams, mlp = tiny_case(n_occ, seed)
+    bg = tuple(np.random.default_rng(seed).uniform(0, 1, 3))
+    dg = device_grid(g)
+    gpu = gpu_render(dg, mlp, cams, bg=bg, early_stop=early, mlp_on=mlp_on)
+    og = O.OracleGrid(g)
+    err, flagged = parity_error(gpu, oracle_variants(og, mlp, cams, bg=bg, early_stop=early, mlp_on=mlp_on))
+    say(f"  rays={len(err)} max_err={err.max():.3e} near_threshold={flagged}")
+    assert err.max() <= TOL_F32
+
+
+def test_tiny_launch_modes_agree_bitwise():
+    g, cams, mlp = tiny_case(64, 1)
+    dg = device_grid(g)
+    base = gpu_render(dg, mlp, cams)
+    n = base.shape[0]
+    for kw in (dict(persistent=True), dict(persistent=True, graph=True)):
+        say(f"launch mode {kw}")
+        assert np.array_equal(gpu_render(dg, mlp, cams, **kw), base)
+    ids = np.random.default_rng(0).permutation(n)[: n // 3]
+    say("list mode")
+    assert np.array_equal(gpu_render(dg, mlp, cams, ids=ids), base[ids])
+    assert np.array_equal(gpu_render(dg, mlp, cams), base)  # deterministic
+
+
+@pytest.mark.parametrize("tile", [(8, 8, 1, 2), (16, 4, 2, 4), (4, 16, 4, 8), (32, 2, 1, 16), (64, 1, 2, 1)])
+def test_tuning_shapes_agree_bitwise(tile):
+    g, cams, mlp = tiny_case(64, 1)
+    dg = device_grid(g)
+    h = handle()
+    base = gpu_render(dg, mlp, cams)
+    old = S.snerg_get_tuning(h)
+    try:
+        S.snerg_set_tuning(h, *tile)
+        say(f"tuning {tile}")
+        assert np.array_equal(gpu_render(dg, mlp, cams), base)
+        assert np.array_equal(gpu_render(dg, mlp, cams, persistent=True, graph=True), base)
+    finally:
+        S.snerg_set_tuning(h, *old)
+
+
+@pytest.mark.parametrize("n_occ,seed,early", [(8, 0, False), (200, 2, False), (200, 2, True), (64, 5, True)])
+def test_visits_and_counters_bit_exact(n_occ, seed, early):
+    say(f"trace n_occ={n_occ} seed={seed} early={early}")
+    g, cams, _ = tiny_case(n_occ, seed)
+    dg = device_grid(g)
+    vis, cnt, ctr = S.trace_visits(handle(), dg, cams, opts=S.make_opts(early_stop=early, mlp_on=False),
+                                   max_visits=64)
+    torch.cuda.synchronize()
+    vis, cnt, ctr = vis.cpu().numpy(), cnt.cpu().numpy(), ctr.cpu().numpy()
+    og = O.OracleGrid(g)
+    ovis, ocnt = O.trace_visits(og, cams, early_stop=early, max_visits=64)
+    octr = O.render(og, None, cams, early_stop=early, mlp_on=False)["counters"]
+    if early:
+        # rays whose stop decision is within the band may differ in their tail
+        alt = [O.render(og, None, cams, early_stop=True, mlp_on=False, t_stop=1e-3 * f)["counters"]
+               for f in (1 - 1e-5, 1 + 1e-5)]
+        same = np.all(octr == alt[0], axis=1) & np.all(octr == alt[1], axis=1)
+    else:
+        same = np.ones(len(cnt), bool)
+    say(f"  rays={len(cnt)} near_threshold={int((~same).sum())} max_count={int(ocnt.max())}")
+    assert np.array_equal(cnt[same], ocnt[same])
+    assert np.array_equal(ctr[same], octr[same])
+    assert np.array_equal(vis[same], ovis[same])
+
+
+def test_plain512_frame_sampled_rays():
+    say("plain512: full 800x800 frame, 12000 sampled rays vs oracle")
+    cfg = W.config("plain512")
+    g, cams, mlp = cfg["grid"], cfg["cams"], cfg["mlp"]
+    dg = device_grid(g)
+    frame = gpu_render(dg, mlp, cams)
+    rng = np.random.default_rng(7)
+    ids = np.sort(rng.choice(frame.shape[0], 12000, replace=False))
+    og = O.OracleGrid(g)
+    err, flagged = parity_error(frame[ids], oracle_variants(og, mlp, cams, ids=ids))
+    say(f"  max_err={err.max():.3e} near_threshold={flagged} hit_frac={(frame[ids, 3] > 0).mean():.3f}")
+    assert err.max() <= TOL_F32
+    assert np.array_equal(gpu_render(dg, mlp, cams, ids=ids), frame[ids])
+    vis, cnt, ctr = S.trace_visits(handle(), dg, cams, ray_ids=torch.from_numpy(ids).cuda(),
+                                   opts=S.make_opts(early_stop=False, mlp_on=False), max_visits=48)
+    torch.cuda.synchronize()
+    ovis, ocnt = O.trace_visits(og, cams, ray_ids=ids, early_stop=False, max_visits=48)
+    assert np.array_equal(cnt.cpu().numpy(), ocnt) and np.array_equal(vis.cpu().numpy(), ovis)
+
+
+@pytest.mark.parametrize("name", ["tiny", "batched1024"])
+def test_fp16_mlp_error_report(name):
+    cfg = W.config(name)
+    g, cams, mlp = cfg["grid"], cfg["cams"], cfg["mlp"]
+    dg = device_grid(g)
+    say(f"fp16 {name}: persistent graph launch over {sum(c.n_rays for c in cams)} rays")
+    frame = gpu_render(dg, mlp, cams, fp16=True, persistent=True, graph=True)
+    n = frame.shape[0]
+    ids = np.sort(np.random.default_rng(3).choice(n, min(n, 8000), replace=False))
+    og = O.OracleGrid(g)
+    err, flagged = parity_error(frame[ids], oracle_variants(og, mlp, cams, ids=ids))
+    f32 = gpu_render(dg, mlp, cams, ids=ids)
+    err32, _ = parity_error(f32, oracle_variants(og, mlp, cams, ids=ids))
+    say(f"  fp16 max_err={err.max():.3e} fp32 max_err={err32.max():.3e} near_threshold={flagged}")
+    assert err.max() <= TOL_F16
+    assert err32.max() <= TOL_F32
+
+
+def test_float32_grid_forward():
+    say("float32 shadow grid forward")
+    g, cams, mlp = tiny_case(120, 6)
+    rng = np.random.default_rng(1)
+    d = g.dens / 255.0
+    vals = (np.where(d > 0, d + 0.01 * rng.uniform(-1, 1, d.shape), 0.0).astype(np.float32),
+            (g.rgb / 255.0 + 0.01 * rng.uniform(-1, 1, g.rgb.shape)).astype(np.float32),
+            (g.feat / 255.0 + 0.01 * rng.uniform(-1, 1, g.feat.shape)).astype(np.float32))
+    dg = device_grid(g, vals)
+    gpu = gpu_render(dg, mlp, cams)
+    og = O.OracleGrid(g, values=vals)
+    err, _ = parity_error(gpu, oracle_variants(og, mlp, cams))
+    say(f"  max_err={err.max():.3e}")
+    assert err.max() <= TOL_F32
+
+
+def test_empty_grid_and_out_of_range_ids():
+    g, cams, mlp = tiny_case(64, 1)
+    bg = (0.1, 0.2, 0.3)
+    empty = W.Grid(g.N, g.B, np.full_like(g.indirection, -1), g.dens, g.rgb, g.feat)
+    say("empty indirection")
+    out = gpu_render(device_grid(empty), mlp, cams, bg=bg)
+    assert np.array_equal(out, np.tile(np.array([0.1, 0.2, 0.3, 0.0], np.float32), (out.shape[0], 1)))
+    # atlas ids >= n_blocks read as empty macroblocks
+    bad = W.Grid(g.N, g.B, g.indirection.copy(), g.dens, g.rgb, g.feat)
+    occ = np.flatnonzero(bad.indirection >= 0)
+    bad.indirection[occ[::3]] = 10 ** 6
+    ref = W.Grid(g.N, g.B, g.indirection.copy(), g.dens, g.rgb, g.feat)
+    ref.indirection[occ[::3]] = -1
+    say("out-of-range atlas ids")
+    assert np.array_equal(gpu_render(device_grid(bad), mlp, cams), gpu_render(device_grid(ref), mlp, cams))
+
+
+def test_zero_rays_is_a_no_op():
+    g, cams, mlp = tiny_case(8, 0)
+    dg = device_grid(g)
+    out = torch.full((1, 4), 7.0, device="cuda")
+    S.snerg_render(handle(), dg.struct(), S.mlp_tensor(mlp), S.make_cameras(cams),
+                   torch.zeros(1, dtype=torch.int64, device="cuda"), 0, S.make_opts(), out)
+    torch.cuda.synchronize()
+    assert torch.all(out == 7.0)
