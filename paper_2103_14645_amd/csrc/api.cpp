@@ -43,6 +43,7 @@ int check_shape(int32_t N, int32_t B, int32_t n_blocks, int32_t dtype) {
     if (N > 16384) return fail(SNERG_ERR_RANGE, "N > 16384 overflows the Q16 lattice in int32");
     if (n_blocks < 0) return fail(SNERG_ERR_INVALID_ARG, "n_blocks must be >= 0");
     const int64_t G = N / B;
+    if (G > 64) return fail(SNERG_ERR_UNSUPPORTED, "N/B > 64: the macroblock occupancy table must fit in LDS");
     if (n_blocks > G * G * G) return fail(SNERG_ERR_INVALID_ARG, "n_blocks exceeds (N/B)^3");
     return SNERG_OK;
 }
@@ -109,13 +110,15 @@ GridArgs grid_args(const snerg_grid* g) {
     const uint8_t* p = static_cast<const uint8_t*>(g->packed);
     GridArgs a;
     a.ind = g->indirection;
-    a.block_lin = reinterpret_cast<const int32_t*>(p + L.off_lin);
-    a.mask = reinterpret_cast<const uint32_t*>(p + L.off_mask);
-    a.vox = p + L.off_vox;
+    a.occ = reinterpret_cast<const uint2*>(p + L.off_occ);
+    a.rank_lin = reinterpret_cast<const int32_t*>(p + L.off_rank_lin);
+    a.rank_id = reinterpret_cast<const int32_t*>(p + L.off_rank_id);
+    a.rec = p + L.off_rec;
     a.N = L.N; a.B = L.B; a.logB = L.logB; a.G = L.G; a.Bp = L.Bp; a.Bc = L.Bc;
-    a.mask_words = L.mask_words;
+    a.n_words = L.n_words;
     a.n_blocks = g->n_blocks;
-    a.vox_stride = L.vox_stride;
+    a.rec_stride = L.rec_stride;
+    a.dist_bytes = L.dist_bytes;
     a.sigma_scale = g->sigma_scale;
     return a;
 }

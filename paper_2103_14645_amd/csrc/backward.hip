@@ -54,13 +54,16 @@ __device__ __forceinline__ float wave_sum(float v) {
 template <int MLP>
 __global__ __launch_bounds__(256) void k_backward(BackwardArgs a) {
     __shared__ float stage[kBwdMaxWaves][64][kStageRow];
+    extern __shared__ uint2 s_occ[];
+    for (int w = threadIdx.x; w < a.grid.n_words; w += blockDim.x) s_occ[w] = a.grid.occ[w];
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int wpg = blockDim.x >> 6;
     const GridArgs& g = a.grid;
     const float delta = 1.0f / float(g.N);
     const float kx = g.sigma_scale * delta;
-    const float* __restrict__ W = a.mlp;
+    cfloat* W = as_const(a.mlp);
 
     float4v acc1[3] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
     float4v acc2 = {0.f, 0.f, 0.f, 0.f}, acc3 = {0.f, 0.f, 0.f, 0.f};
@@ -223,11 +226,10 @@ __global__ __launch_bounds__(256) void k_backward(BackwardArgs a) {
             const float t_stop = a.opts.t_stop;
             const bool early = a.opts.early_stop != 0;
             march_ray(
-                g, o, s, [](int32_t, bool) {}, []() {},
-                [&](int64_t, int32_t id, const int32_t p[3], const int32_t fr[3]) {
+                g, s_occ, o, s, [](int32_t, bool) {}, [](int32_t) {},
+                [&](int64_t, int32_t rk, const uint8_t* vox, const int32_t p[3], const int32_t fr[3]) {
                     Sample smp;
-                    const uint8_t* blk = g.vox + int64_t(id) * g.vox_stride;
-                    gather_f32(blk, g.Bp, p, fr, smp);
+                    gather_f32(vox, g.Bp, p, fr, smp);
                     if (!smp.active) return false;
                     const float x = smp.sigma_raw * kx;
                     const float e = __expf(-x);
@@ -240,7 +242,8 @@ __global__ __launch_bounds__(256) void k_backward(BackwardArgs a) {
                     T *= e;
                     const float gsig = delta * (T * ek - (E - Pk) - tail);
                     // scatter through the trilinear weights
-                    const int32_t lin = g.block_lin[id];
+                    const int32_t lin = g.rank_lin[rk];
+                    const int32_t id = g.rank_id[rk];
                     const int32_t b[3] = {lin % g.G, (lin / g.G) % g.G, lin / (g.G * g.G)};
                     float wc[8];
                     corner_weights(fr, wc);
@@ -302,10 +305,11 @@ __global__ void k_reduce_rows(const float* __restrict__ partial, int rows, float
 
 hipError_t launch_backward(const BackwardArgs& a, int n_groups, hipStream_t s) {
     if (n_groups <= 0) return hipSuccess;
+    const size_t lds = size_t(a.grid.n_words) * sizeof(uint2);
     if (a.mlp_mode == kMlpOff)
-        hipLaunchKernelGGL(k_backward<kMlpOff>, dim3(n_groups), dim3(64 * kBwdMaxWaves), 0, s, a);
+        hipLaunchKernelGGL(k_backward<kMlpOff>, dim3(n_groups), dim3(64 * kBwdMaxWaves), lds, s, a);
     else
-        hipLaunchKernelGGL(k_backward<kMlpF32>, dim3(n_groups), dim3(64 * kBwdMaxWaves), 0, s, a);
+        hipLaunchKernelGGL(k_backward<kMlpF32>, dim3(n_groups), dim3(64 * kBwdMaxWaves), lds, s, a);
     return hipGetLastError();
 }
 

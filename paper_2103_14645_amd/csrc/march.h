@@ -104,34 +104,63 @@ __device__ __forceinline__ void gather_f32(const uint8_t* __restrict__ blk, int 
     smp.active = act;
 }
 
-// Visits every lattice sample of a ray that lies in an occupied macroblock
-// and passes the cell-mask pre-test, in order.  For each one f(k, id, p, fr)
-// is called with the atlas block id, padded cell and 16-bit fractions; f
-// returns true to stop the march.  Per-block and per-sample hooks feed the
-// visit trace.  Returns the k at which f stopped the march, or -1.
+// Occupancy lookup: rank of macroblock `lin` in scan order, or -1 if empty.
+__host__ __device__ __forceinline__ int32_t block_rank(const uint2* occ, int32_t lin, int32_t n_blocks) {
+    const uint2 e = occ[lin >> 5];
+    const uint32_t j = uint32_t(lin) & 31u;
+    if (!((e.x >> j) & 1u)) return -1;
+    const int32_t r = int32_t(e.y) + __builtin_popcount(e.x & ((1u << j) - 1u));
+    return r < n_blocks ? r : -1;
+}
+
+// Samples the ray may skip from a cell at Chebyshev distance d >= 1 from the
+// nearest active cell: after j steps every coordinate has moved by at most
+// j*smax in Q16, so the cell index by at most ceil(j*smax / 2^16), and all
+// j with j*smax <= (d-1) 2^16 land in inactive cells.  Returns that largest
+// j plus one (the current sample is inactive too).
+__host__ __device__ __forceinline__ int32_t skip_steps(int32_t d, int32_t smax, float inv_smax) {
+    const int32_t D = (d - 1) << 16;
+    int32_t m = (int32_t)__builtin_floorf((float)D * inv_smax);
+    if ((m + 1) * smax <= D) ++m;
+    if (m > 0 && m * smax > D) --m;
+    return m + 1;
+}
+
+// Visits, in order, every lattice sample of a ray that lies in an occupied
+// macroblock and in an active cell (cells closer than their distance value
+// to the current one are skipped in one step).  on_sample(k, rank, vox, p,
+// fr) gets the block's rank, its padded voxels, the padded cell p and the
+// 16-bit fractions, and returns true to stop the march.  on_block(lin, occ)
+// and on_inblock(n) (n samples inside an occupied block passed) feed the
+// visit trace.  `occ` is the occupancy table (usually staged in LDS).
+// Returns the k at which on_sample stopped the march, or -1.
 template <typename OnBlock, typename OnInBlock, typename OnSample>
-__host__ __device__ __forceinline__ int64_t march_ray(const GridArgs& g, const int64_t o[3], const int32_t s[3],
-                                             OnBlock&& on_block, OnInBlock&& on_inblock,
-                                             OnSample&& on_sample) {
+__host__ __device__ __forceinline__ int64_t march_ray(const GridArgs& g, const uint2* occ, const int64_t o[3],
+                                                      const int32_t s[3], OnBlock&& on_block,
+                                                      OnInBlock&& on_inblock, OnSample&& on_sample) {
     const int bs = 16 + g.logB;
     const int64_t L = int64_t(g.N) << 16;
     int64_t klo, khi;
     if (!entry_range(o, s, L, klo, khi)) return -1;
     float inv[3];
     int32_t P[3];
+    int32_t smax = 1;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        inv[a] = s[a] != 0 ? 1.0f / float(s[a] < 0 ? -s[a] : s[a]) : 0.0f;
+        const int32_t sa = s[a] < 0 ? -s[a] : s[a];
+        smax = sa > smax ? sa : smax;
+        inv[a] = sa != 0 ? 1.0f / float(sa) : 0.0f;
         P[a] = int32_t(o[a] + klo * int64_t(s[a]));  // inside [0, N 2^16)
     }
+    const float inv_smax = 1.0f / float(smax);
     int64_t k = klo;
     while (k <= khi) {
         int32_t b[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) b[a] = P[a] >> bs;
-        // Guards: the exact integer arithmetic above keeps P inside the grid
-        // and every sample of [k, kn) inside block b; these checks make any
-        // violation end the ray instead of indexing outside the buffers.
+        // Guards: the exact integer arithmetic keeps P inside the grid and
+        // every sample of [k, kn) inside block b; these checks end the ray
+        // instead of indexing outside the buffers should that ever fail.
         if ((unsigned)b[0] >= (unsigned)g.G || (unsigned)b[1] >= (unsigned)g.G || (unsigned)b[2] >= (unsigned)g.G)
             return -1;
         int32_t nstep = block_steps(P, s, inv, b, bs);
@@ -141,24 +170,33 @@ __host__ __device__ __forceinline__ int64_t march_ray(const GridArgs& g, const i
             --nstep;
         const int64_t kn = (k + int64_t(nstep)) < (khi + 1) ? (k + int64_t(nstep)) : (khi + 1);
         const int32_t lin = (b[2] * g.G + b[1]) * g.G + b[0];
-        const int32_t id = g.ind[lin];
-        const bool occ = (id >= 0) && (id < g.n_blocks);
-        on_block(lin, occ);
-        if (occ) {
-            const uint32_t* __restrict__ mk = g.mask + int64_t(id) * g.mask_words;
+        const int32_t r = block_rank(occ, lin, g.n_blocks);
+        on_block(lin, r >= 0);
+        if (r >= 0) {
+            const uint8_t* __restrict__ dist = g.rec + int64_t(r) * g.rec_stride;
+            const uint8_t* __restrict__ vox = dist + g.dist_bytes;
             int32_t q[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) q[a] = P[a] - (b[a] << bs) + 32768;  // padded Q16 coordinate
-            for (int64_t kk = k; kk < kn; ++kk) {
+            int32_t left = int32_t(kn - k);
+            int64_t kk = k;
+            while (left > 0) {
                 const int32_t p[3] = {q[0] >> 16, q[1] >> 16, q[2] >> 16};
-                const int32_t cell = (p[2] * g.Bc + p[1]) * g.Bc + p[0];
-                on_inblock();
-                if ((mk[cell >> 5] >> (cell & 31)) & 1u) {
+                const int32_t d = dist[(p[2] * g.Bc + p[1]) * g.Bc + p[0]];
+                int32_t adv = 1;
+                if (d == 0) {
+                    on_inblock(1);
                     const int32_t fr[3] = {q[0] & 0xFFFF, q[1] & 0xFFFF, q[2] & 0xFFFF};
-                    if (on_sample(kk, id, p, fr)) return kk;
+                    if (on_sample(kk, r, vox, p, fr)) return kk;
+                } else {
+                    adv = skip_steps(d, smax, inv_smax);
+                    adv = adv < left ? adv : left;
+                    on_inblock(adv);
                 }
+                kk += adv;
+                left -= adv;
 #pragma unroll
-                for (int a = 0; a < 3; ++a) q[a] += s[a];
+                for (int a = 0; a < 3; ++a) q[a] += adv * s[a];
             }
         }
         const int32_t adv = int32_t(kn - k);

@@ -36,25 +36,31 @@ __device__ __forceinline__ void encode_x(const float C[3], const float V[4], con
 
 __device__ __forceinline__ float sigmoid_f32(float z) { return 1.0f / (1.0f + __expf(-z)); }
 
-__device__ __forceinline__ void mlp_forward_f32(const float* __restrict__ W, const float C[3],
+// One ray per lane.  Layer 1 runs hidden unit by hidden unit in a rolled
+// loop; each h1_j is folded into the 16 layer-2 accumulators as soon as it
+// exists, so only x, the accumulators and one weight row are live (the
+// weights arrive through scalar loads; unrolled, their hoisting overflows
+// the scalar register file).  Summation order per output is unchanged:
+// bias first, then inputs in index order.
+__device__ __forceinline__ void mlp_forward_f32(cfloat* W, const float C[3],
                                                 const float V[4], const float d[3], float R[3]) {
     float x[kMlpIn];
     encode_x(C, V, d, x);
-    float h1[kMlpH], h2[kMlpH];
+    float h2[kMlpH];
 #pragma unroll
+    for (int k = 0; k < kMlpH; ++k) h2[k] = W[kOffB2 + k];
+#pragma nounroll
     for (int j = 0; j < kMlpH; ++j) {
+        cfloat* row = W + kOffW1 + j * kMlpIn;
         float s = W[kOffB1 + j];
 #pragma unroll
-        for (int i = 0; i < kMlpIn; ++i) s = fmaf(W[kOffW1 + j * kMlpIn + i], x[i], s);
-        h1[j] = fmaxf(s, 0.0f);
+        for (int i = 0; i < kMlpIn; ++i) s = fmaf(row[i], x[i], s);
+        const float h1j = fmaxf(s, 0.0f);
+#pragma unroll
+        for (int k = 0; k < kMlpH; ++k) h2[k] = fmaf(W[kOffW2 + k * kMlpH + j], h1j, h2[k]);
     }
 #pragma unroll
-    for (int j = 0; j < kMlpH; ++j) {
-        float s = W[kOffB2 + j];
-#pragma unroll
-        for (int i = 0; i < kMlpH; ++i) s = fmaf(W[kOffW2 + j * kMlpH + i], h1[i], s);
-        h2[j] = fmaxf(s, 0.0f);
-    }
+    for (int k = 0; k < kMlpH; ++k) h2[k] = fmaxf(h2[k], 0.0f);
 #pragma unroll
     for (int j = 0; j < kMlpOut; ++j) {
         float s = W[kOffB3 + j];
@@ -74,7 +80,7 @@ constexpr int kMaxWavesF16 = 4;
 // A-operand fragment of a row-major [rows][cols] FP32 matrix for a 16x16 tile
 // (rows r0.., cols c0..): lane l holds M[r0 + l%16][c0 + 4(l/16) + j], zero
 // outside [rows, cols).
-__device__ __forceinline__ half4_t a_frag(const float* __restrict__ M, int rows, int cols, int r0, int c0,
+__device__ __forceinline__ half4_t a_frag(cfloat* M, int rows, int cols, int r0, int c0,
                                           int lane) {
     const int r = r0 + (lane & 15);
     const int c = c0 + 4 * (lane >> 4);
@@ -85,7 +91,7 @@ __device__ __forceinline__ half4_t a_frag(const float* __restrict__ M, int rows,
 }
 
 // Accumulator initialised with a bias: lane l holds rows 4(l/16) + v.
-__device__ __forceinline__ float4_t bias_frag(const float* __restrict__ b, int rows, int lane) {
+__device__ __forceinline__ float4_t bias_frag(cfloat* b, int rows, int lane) {
     float4_t v;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -104,7 +110,7 @@ __device__ __forceinline__ half4_t relu_to_half(float4_t v) {
 
 // All 64 lanes of the wavefront must call this together.  Lanes with
 // use == false get R = 0 (their inputs still flow through the tiles).
-__device__ __forceinline__ void mlp_forward_f16_wave(const float* __restrict__ W, bool use, const float C[3],
+__device__ __forceinline__ void mlp_forward_f16_wave(cfloat* W, bool use, const float C[3],
                                                      const float V[4], const float d[3], float R[3]) {
     __shared__ _Float16 xs[kMaxWavesF16][64][kXRow];
     const int lane = threadIdx.x & 63;

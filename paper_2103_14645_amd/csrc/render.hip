@@ -30,23 +30,30 @@ __device__ __forceinline__ void composite(RayAccum& st, const Sample& smp, float
 }
 
 template <int VT>
-__device__ __forceinline__ void march_composite(const RenderArgs& a, const int64_t o[3], const int32_t s[3],
-                                                RayAccum& st) {
+__device__ __forceinline__ void march_composite(const RenderArgs& a, const uint2* occ, const int64_t o[3],
+                                                const int32_t s[3], RayAccum& st) {
     const GridArgs& g = a.grid;
     const float cs = VT == 0 ? (1.0f / 255.0f) : 1.0f;
     const float kx = g.sigma_scale * cs / float(g.N);
     const float t_stop = a.opts.t_stop;
     const bool early = a.opts.early_stop != 0;
     march_ray(
-        g, o, s, [](int32_t, bool) {}, []() {},
-        [&](int64_t, int32_t id, const int32_t p[3], const int32_t fr[3]) {
+        g, occ, o, s, [](int32_t, bool) {}, [](int32_t) {},
+        [&](int64_t, int32_t, const uint8_t* vox, const int32_t p[3], const int32_t fr[3]) {
             Sample smp;
-            const uint8_t* blk = g.vox + int64_t(id) * g.vox_stride;
-            if (VT == 0) gather_u8(blk, g.Bp, p, fr, smp); else gather_f32(blk, g.Bp, p, fr, smp);
+            if (VT == 0) gather_u8(vox, g.Bp, p, fr, smp); else gather_f32(vox, g.Bp, p, fr, smp);
             if (!smp.active) return false;
             composite(st, smp, kx, cs);
             return early && st.T < t_stop;
         });
+}
+
+// Copies the occupancy table into LDS (all threads of the workgroup call this).
+__device__ __forceinline__ const uint2* stage_occupancy(const GridArgs& g) {
+    extern __shared__ uint2 s_occ[];
+    for (int w = threadIdx.x; w < g.n_words; w += blockDim.x) s_occ[w] = g.occ[w];
+    __syncthreads();
+    return s_occ;
 }
 
 // Pixel of lane `lane` in wavefront tile t; false when the tile overhangs the image.
@@ -63,22 +70,22 @@ __device__ __forceinline__ bool tile_pixel(const RenderArgs& a, int64_t t, int l
 }
 
 template <int VT, int MLP>
-__device__ __forceinline__ void render_ray(const RenderArgs& a, bool valid, int ci, int px, int py,
-                                           int64_t out_idx) {
+__device__ __forceinline__ void render_ray(const RenderArgs& a, const uint2* occ, bool valid, int ci, int px,
+                                           int py, int64_t out_idx) {
     RayAccum st = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, 1.0f, false};
     float d[3] = {0.f, 0.f, 1.f};
     if (valid) {
         int64_t o[3];
         int32_t s[3];
         ray_setup(a.cams[ci], a.grid.N, px, py, o, s, d);
-        march_composite<VT>(a, o, s, st);
+        march_composite<VT>(a, occ, o, s, st);
     }
     float R[3] = {0.f, 0.f, 0.f};
     const bool use_mlp = valid && st.gate && a.opts.mlp_on;
     if (MLP == kMlpF32) {
-        if (use_mlp) mlp_forward_f32(a.mlp, st.C, st.V, d, R);
+        if (use_mlp) mlp_forward_f32(as_const(a.mlp), st.C, st.V, d, R);
     } else if (MLP == kMlpF16) {
-        mlp_forward_f16_wave(a.mlp, use_mlp, st.C, st.V, d, R);
+        mlp_forward_f16_wave(as_const(a.mlp), use_mlp, st.C, st.V, d, R);
     }
     if (valid) {
         float4 out;
@@ -95,47 +102,52 @@ __device__ __forceinline__ void render_ray(const RenderArgs& a, bool valid, int 
     }
 }
 
-template <int VT, int MLP>
+// PERSIST selects the persistent kernel (a loop over the global tile queue);
+// the other kernel serves the one-wavefront-per-tile and ray-list launches.
+// They are separate kernels so that each gets its own register allocation.
+template <int VT, int MLP, bool PERSIST>
 __global__ __launch_bounds__(256) void k_render(RenderArgs a) {
+    const uint2* occ = stage_occupancy(a.grid);
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int wpg = blockDim.x >> 6;
-    if (a.mode == kModeList) {
-        const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-        const bool valid = i < a.n_rays;
+    // One inlined copy of the per-ray body; the launch modes differ only in
+    // how a wavefront obtains its next 64 rays (wave-uniform control flow).
+    int64_t t = a.mode == kModeList ? int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63)
+                                    : int64_t(blockIdx.x) * wpg + wave;
+    for (;;) {
+        if (PERSIST) {
+            int64_t v = 0;
+            if (lane == 0) v = atomicAdd(a.tile_counter, 1);
+            t = __shfl(v, 0);
+        }
+        bool valid;
         int ci = 0, px = 0, py = 0;
-        if (valid) {
-            const int64_t r = a.ray_ids[i];
-            ci = find_camera_by_ray(a.cams, a.n_cams, r);
-            const int64_t local = r - a.cams[ci].ray_offset;
-            py = int(local / a.cams[ci].W);
-            px = int(local - int64_t(py) * a.cams[ci].W);
-        }
-        render_ray<VT, MLP>(a, valid, ci, px, py, i);
-    } else if (a.mode == kModeTiles) {
-        const int64_t t = int64_t(blockIdx.x) * wpg + wave;
-        if (t >= a.total_tiles) return;  // wave-uniform
-        int ci, px, py;
-        int64_t rid;
-        const bool valid = tile_pixel(a, t, lane, ci, px, py, rid);
-        render_ray<VT, MLP>(a, valid, ci, px, py, rid);
-    } else {
-        for (;;) {
-            int64_t t = 0;
-            if (lane == 0) t = atomicAdd(a.tile_counter, 1);
-            t = __shfl(t, 0);
+        int64_t out_idx;
+        if (a.mode == kModeList) {
+            if (t >= a.n_rays) break;  // wave-uniform
+            out_idx = t + lane;
+            valid = out_idx < a.n_rays;
+            if (valid) {
+                const int64_t r = a.ray_ids[out_idx];
+                ci = find_camera_by_ray(a.cams, a.n_cams, r);
+                const int64_t local = r - a.cams[ci].ray_offset;
+                py = int(local / a.cams[ci].W);
+                px = int(local - int64_t(py) * a.cams[ci].W);
+            }
+        } else {
             if (t >= a.total_tiles) break;  // wave-uniform; every wave reaches it
-            int ci, px, py;
-            int64_t rid;
-            const bool valid = tile_pixel(a, t, lane, ci, px, py, rid);
-            render_ray<VT, MLP>(a, valid, ci, px, py, rid);
+            valid = tile_pixel(a, t, lane, ci, px, py, out_idx);
         }
+        render_ray<VT, MLP>(a, occ, valid, ci, px, py, out_idx);
+        if (!PERSIST) break;
     }
 }
 
 // Visit trace: one lane per listed ray (or per ray id when the list is absent).
 template <int VT>
 __global__ __launch_bounds__(256) void k_trace(RenderArgs a) {
+    const uint2* occ = stage_occupancy(a.grid);
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= a.n_rays) return;
     const int64_t r = a.ray_ids ? a.ray_ids[i] : i;
@@ -154,7 +166,7 @@ __global__ __launch_bounds__(256) void k_trace(RenderArgs a) {
     int32_t n_trav = 0, n_occ = 0, n_in = 0, n_act = 0;
     int32_t* vis = a.visits ? a.visits + i * a.max_visits : nullptr;
     const int64_t stop = march_ray(
-        g, o, s,
+        g, occ, o, s,
         [&](int32_t lin, bool occ) {
             ++n_trav;
             if (occ) {
@@ -162,11 +174,10 @@ __global__ __launch_bounds__(256) void k_trace(RenderArgs a) {
                 ++n_occ;
             }
         },
-        [&]() { ++n_in; },
-        [&](int64_t, int32_t id, const int32_t p[3], const int32_t fr[3]) {
+        [&](int32_t n) { n_in += n; },
+        [&](int64_t, int32_t, const uint8_t* vox, const int32_t p[3], const int32_t fr[3]) {
             Sample smp;
-            const uint8_t* blk = g.vox + int64_t(id) * g.vox_stride;
-            if (VT == 0) gather_u8(blk, g.Bp, p, fr, smp); else gather_f32(blk, g.Bp, p, fr, smp);
+            if (VT == 0) gather_u8(vox, g.Bp, p, fr, smp); else gather_f32(vox, g.Bp, p, fr, smp);
             if (!smp.active) return false;
             ++n_act;
             composite(st, smp, kx, cs);
@@ -191,7 +202,11 @@ static hipError_t launch_render_t(const RenderArgs& a, int wpg, int n_groups, hi
     else if (a.mode == kModeTiles) blocks = unsigned((a.total_tiles + wpg - 1) / wpg);
     else blocks = unsigned(n_groups);
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_render<VT, MLP>), dim3(blocks), dim3(threads), 0, s, a);
+    const size_t lds = size_t(a.grid.n_words) * sizeof(uint2);
+    if (a.mode == kModePersistent)
+        hipLaunchKernelGGL((k_render<VT, MLP, true>), dim3(blocks), dim3(threads), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_render<VT, MLP, false>), dim3(blocks), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
@@ -210,8 +225,9 @@ hipError_t launch_render(const RenderArgs& a, int vt, int mlp_mode, int wpg, int
 hipError_t launch_trace(const RenderArgs& a, int vt, hipStream_t s) {
     if (a.n_rays <= 0) return hipSuccess;
     const unsigned blocks = unsigned((a.n_rays + 255) / 256);
-    if (vt == 0) hipLaunchKernelGGL(k_trace<0>, dim3(blocks), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(k_trace<1>, dim3(blocks), dim3(256), 0, s, a);
+    const size_t lds = size_t(a.grid.n_words) * sizeof(uint2);
+    if (vt == 0) hipLaunchKernelGGL(k_trace<0>, dim3(blocks), dim3(256), lds, s, a);
+    else hipLaunchKernelGGL(k_trace<1>, dim3(blocks), dim3(256), lds, s, a);
     return hipGetLastError();
 }
 

@@ -1,19 +1,26 @@
 // Device-side data layouts and helpers of the gfx950 SNeRG renderer.
 //
-// Packed grid (written by k_pack_*, read by the render/backward kernels):
-//   [block_lin: n_blocks int32]       linear indirection index of each atlas block
-//   [mask:      n_blocks * mask_words uint32]
-//       bit ((pz*(B+1) + py)*(B+1) + px) of a block is set when any of the 8
-//       voxels (px..px+1, py..py+1, pz..pz+1) of the block's apron copy has
-//       non-zero density.  Cell (px,py,pz) is the trilinear cell whose
-//       lower corner is local voxel (px-1, py-1, pz-1).
-//   [voxels:    n_blocks * (B+2)^3 * VSIZE bytes]
-//       padded copy of the block: local voxel v in [-1, B] per axis at
-//       ((v_z+1)*(B+2) + (v_y+1))*(B+2) + (v_x+1); voxels of neighbouring
-//       occupied blocks are copied in, outside/empty ones are zero.
-//       Channels interleaved per voxel: density, r, g, b, f0..f3
-//       (VSIZE = 8 bytes for uint8, 32 bytes for float32).
-// Every section starts on a 256-byte boundary.
+// Packed grid (written by the pack kernels, read by render/backward):
+//   [occ:      n_words x {uint32 bits, int32 rank}]  n_words = ceil(G^3 / 32)
+//       bit j of word w is set when macroblock lin = 32 w + j (indirection
+//       order) holds a valid atlas id; `rank` counts the set bits of all
+//       earlier words.  The rank of an occupied macroblock (its position in
+//       scan order) indexes the per-block records below.
+//   [rank_lin: n_blocks int32]  indirection index of rank r
+//   [rank_id:  n_blocks int32]  atlas id of rank r (canonical layout)
+//   [records:  n_blocks x rec_stride bytes], rank order, each:
+//       dist: (B+1)^3 bytes.  Cell (cx, cy, cz), c in [0, B], is the
+//           trilinear cell whose lower corner is local voxel c - 1; it is
+//           active when any of its 8 corner voxels has non-zero density.
+//           dist holds the Chebyshev (L-inf) distance, in cells, from the
+//           cell to the nearest active cell of the same record (0 = active,
+//           capped at 255), at ((cz*(B+1) + cy)*(B+1) + cx).
+//       vox (16-byte aligned): padded copy of the block, local voxel v in
+//           [-1, B] per axis at ((v_z+1)*(B+2) + (v_y+1))*(B+2) + (v_x+1);
+//           voxels of neighbouring occupied blocks are copied in,
+//           outside/empty ones are zero.  Channels interleaved per voxel:
+//           density, r, g, b, f0..f3 (8 bytes for uint8, 32 for float32).
+// Sections start on 256-byte boundaries; records are 256-byte aligned.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -46,10 +53,11 @@ struct PackedLayout {
     int32_t N, B, logB, G;
     int32_t Bp;          // B + 2
     int32_t Bc;          // B + 1
-    int32_t mask_words;  // uint32 words per block
+    int32_t n_words;     // occupancy words
     int32_t vsize;       // bytes per voxel
-    int64_t off_lin, off_mask, off_vox;
-    int64_t vox_stride;  // bytes per padded block
+    int64_t off_occ, off_rank_lin, off_rank_id, off_rec;
+    int64_t dist_bytes;  // (B+1)^3 rounded up to 16
+    int64_t rec_stride;  // bytes per block record
     int64_t total;
 };
 
@@ -65,27 +73,38 @@ inline PackedLayout make_layout(int32_t N, int32_t B, int32_t n_blocks, int32_t 
     L.G = N / B;
     L.Bp = B + 2;
     L.Bc = B + 1;
-    int64_t cells = int64_t(L.Bc) * L.Bc * L.Bc;
-    L.mask_words = int32_t((cells + 31) / 32);
+    const int64_t G3 = int64_t(L.G) * L.G * L.G;
+    L.n_words = int32_t((G3 + 31) / 32);
     L.vsize = vsize;
-    L.off_lin = 0;
-    L.off_mask = align256(int64_t(n_blocks) * 4);
-    L.off_vox = L.off_mask + align256(int64_t(n_blocks) * L.mask_words * 4);
-    L.vox_stride = int64_t(L.Bp) * L.Bp * L.Bp * vsize;
-    L.total = L.off_vox + int64_t(n_blocks) * L.vox_stride;
+    L.off_occ = 0;
+    L.off_rank_lin = align256(int64_t(L.n_words) * 8);
+    L.off_rank_id = L.off_rank_lin + align256(int64_t(n_blocks) * 4);
+    L.off_rec = L.off_rank_id + align256(int64_t(n_blocks) * 4);
+    L.dist_bytes = (int64_t(L.Bc) * L.Bc * L.Bc + 15) & ~int64_t(15);
+    L.rec_stride = align256(L.dist_bytes + int64_t(L.Bp) * L.Bp * L.Bp * vsize);
+    L.total = L.off_rec + int64_t(n_blocks) * L.rec_stride;
     return L;
 }
 
+// Largest grid whose occupancy table is staged in LDS: (N/B)^3 <= 2^18.
+constexpr int kMaxOccWords = (1 << 18) / 32;
+
 // Grid as a kernel argument.
 struct GridArgs {
-    const int32_t* ind;
-    const int32_t* block_lin;
-    const uint32_t* mask;
-    const uint8_t* vox;
-    int32_t N, B, logB, G, Bp, Bc, mask_words, n_blocks;
-    int64_t vox_stride;
+    const int32_t* ind;       // canonical indirection (atlas ids)
+    const uint2* occ;         // {bits, rank} per 32 macroblocks
+    const int32_t* rank_lin;
+    const int32_t* rank_id;
+    const uint8_t* rec;       // block records in rank order
+    int32_t N, B, logB, G, Bp, Bc, n_words, n_blocks;
+    int64_t rec_stride, dist_bytes;
     float sigma_scale;
 };
+
+// Read-only parameters viewed through the constant address space: loads at
+// wavefront-uniform addresses become scalar (SMEM) loads into SGPRs.
+typedef const __attribute__((address_space(4))) float cfloat;
+__device__ __forceinline__ cfloat* as_const(const float* p) { return (cfloat*)p; }
 
 struct RenderOpts {
     float bg[3];

@@ -20,7 +20,8 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsnerg.so")
+# SNERG_LIB selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("SNERG_LIB") or os.path.join(_HERE, "libsnerg.so")
 
 SNERG_OK = 0
 SNERG_ERR_INVALID_ARG = -1

@@ -39,12 +39,20 @@ def test_status_strings():
 
 
 def test_packed_size_layout_and_errors():
-    # block_lin (256-aligned) + mask ((B+1)^3 bits per block, 256-aligned) + (B+2)^3 voxels
+    # occupancy {bits, rank} words + rank->lin + rank->id (each 256-aligned),
+    # then per block a 256-aligned record: (B+1)^3 distance bytes (16-aligned)
+    # and (B+2)^3 padded voxels
+    def a256(x):
+        return (x + 255) // 256 * 256
+
     n = 433
-    words = math.ceil(33 ** 3 / 32)
-    expect = ((n * 4 + 255) // 256) * 256 + (((n * words * 4) + 255) // 256) * 256 + n * 34 ** 3 * 8
-    assert S.snerg_packed_size(512, 32, n, S.SNERG_U8) == expect
-    assert S.snerg_packed_size(512, 32, n, S.SNERG_F32) == expect + n * 34 ** 3 * 24
+    head = a256(math.ceil(16 ** 3 / 32) * 8) + 2 * a256(n * 4)
+    dist = (33 ** 3 + 15) // 16 * 16
+    assert S.snerg_packed_size(512, 32, n, S.SNERG_U8) == head + n * a256(dist + 34 ** 3 * 8)
+    assert S.snerg_packed_size(512, 32, n, S.SNERG_F32) == head + n * a256(dist + 34 ** 3 * 32)
+    with pytest.raises(S.SnergError) as e:
+        S.snerg_packed_size(4096, 32, 1, S.SNERG_U8)          # N/B = 128: occupancy table too large for LDS
+    assert e.value.code == S.SNERG_ERR_UNSUPPORTED
     for args, code in [((512, 24, 1, 0), S.SNERG_ERR_UNSUPPORTED), ((500, 32, 1, 0), S.SNERG_ERR_UNSUPPORTED),
                        ((32768, 32, 1, 0), S.SNERG_ERR_RANGE), ((512, 32, 1, 7), S.SNERG_ERR_UNSUPPORTED),
                        ((512, 32, -1, 0), S.SNERG_ERR_INVALID_ARG),
