@@ -147,6 +147,8 @@ struct snerg_handle {
     int32_t* d_counter = nullptr;
     float* d_partial = nullptr;
     size_t partial_cap = 0;
+    float* d_gcv = nullptr;  // per-ray g_C, g_V of the backward pass
+    size_t gcv_cap = 0;
     snerg_tuning tuning = {8, 8, 4, 8};
     // cached graph of {counter reset, persistent render}
     hipGraphExec_t graph_exec = nullptr;
@@ -205,14 +207,15 @@ int upload_cams(snerg_handle* h, const snerg_camera* cams, int32_t n_cams, int t
     return SNERG_OK;
 }
 
-int ensure_partial(snerg_handle* h, size_t rows) {
-    const size_t need = rows * kMlpParams;
-    if (need <= h->partial_cap) return SNERG_OK;
+// Grows a handle-owned float buffer (waits for queued work before freeing).
+int ensure_buffer(float** buf, size_t* cap, size_t need) {
+    if (need <= *cap) return SNERG_OK;
     HIP_TRY(hipDeviceSynchronize());
-    if (h->d_partial) HIP_TRY(hipFree(h->d_partial));
-    h->d_partial = nullptr;
-    HIP_TRY(hipMalloc(&h->d_partial, need * sizeof(float)));
-    h->partial_cap = need;
+    if (*buf) HIP_TRY(hipFree(*buf));
+    *buf = nullptr;
+    *cap = 0;
+    HIP_TRY(hipMalloc(buf, need * sizeof(float)));
+    *cap = need;
     return SNERG_OK;
 }
 
@@ -347,6 +350,7 @@ int snerg_destroy(snerg_handle* h) {
     if (h->h_cams) hipHostFree(h->h_cams);
     if (h->d_counter) hipFree(h->d_counter);
     if (h->d_partial) hipFree(h->d_partial);
+    if (h->d_gcv) hipFree(h->d_gcv);
     if (h->cams_copied) hipEventDestroy(h->cams_copied);
     if (h->cap_stream) hipStreamDestroy(h->cap_stream);
     delete h;
@@ -438,12 +442,14 @@ int snerg_render_backward(snerg_handle* h, const snerg_grid* grid, const float* 
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t B3 = int64_t(grid->B) * grid->B * grid->B;
     const int64_t nv = int64_t(grid->n_blocks) * B3;
-    const int waves = 4;
-    int64_t want = (n_rays + 64 * waves - 1) / (64 * waves);
-    const int n_groups = int(std::max<int64_t>(1, std::min<int64_t>(want, int64_t(h->n_cu) * 4)));
+    const int64_t want = (n_rays + 127) / 128;
+    const int n_groups = int(std::max<int64_t>(1, std::min<int64_t>(want, int64_t(h->n_cu) * 8)));
     const int mlp_mode = opts->mlp_on ? kMlpF32 : kMlpOff;
+    const int rows = backward_partial_rows(n_groups);
     if (mlp_mode != kMlpOff) {
-        rc = ensure_partial(h, size_t(n_groups) * waves);
+        rc = ensure_buffer(&h->d_partial, &h->partial_cap, size_t(rows) * kMlpParams);
+        if (rc) return rc;
+        rc = ensure_buffer(&h->d_gcv, &h->gcv_cap, size_t(std::max<int64_t>(n_rays, 1)) * 8);
         if (rc) return rc;
     }
     int64_t total_tiles = 0;
@@ -467,11 +473,12 @@ int snerg_render_backward(snerg_handle* h, const snerg_grid* grid, const float* 
     a.aux = aux;
     a.grad_rgba = grad_rgba;
     a.g_mlp_partial = h->d_partial;
+    a.gcv = h->d_gcv;
     a.grad_dens = grad_dens;
     a.grad_rgb = grad_rgb;
     a.grad_feat = grad_feat;
     HIP_TRY(launch_backward(a, n_groups, s));
-    if (mlp_mode != kMlpOff) HIP_TRY(launch_reduce_mlp(h->d_partial, n_groups * waves, grad_mlp, s));
+    if (mlp_mode != kMlpOff) HIP_TRY(launch_reduce_mlp(h->d_partial, rows, grad_mlp, s));
     return SNERG_OK;
 }
 

@@ -1,18 +1,23 @@
 // Adjoint of the render (fine-tuning by a pixel loss, Eq. 3, Section 5.5).
 //
 // For each ray with output gradient g = dL/d(rgb, alpha):
-//  1. MLP backward (Eq. 7): g_C = g_rgb + (J_R^T g_rgb)[0:3],
-//     g_V = (J_R^T g_rgb)[3:7]; the weight gradients of the wavefront's 64
-//     rays are summed with FP32 MFMA outer products (rays are the K
-//     dimension) into per-wavefront accumulators.
-//  2. Re-march the same samples (nothing per sample was stored).  With
-//     E = g_C . C_d + g_V . V (from the forward's saved C_d, V), the running
-//     prefix P_k = sum_{j<=k} w_j e_j, e_k = g_C . c_k + g_V . v_k and
-//     dL/dT_N = g_rgb . bg - g_alpha, Eq. 2/5/6 give
+//  K1 (k_mlp_backward, only with the MLP on): MLP backward (Eq. 7):
+//     g_C = g_rgb + (J_R^T g_rgb)[0:3], g_V = (J_R^T g_rgb)[3:7], written per
+//     ray; the weight gradients of the wavefront's 64 rays are summed with
+//     FP32 MFMA outer products (rays are the K dimension) into per-wavefront
+//     partial rows, reduced afterwards.
+//  K2 (k_march_backward): re-march the same samples (nothing per sample was
+//     stored).  With E = g_C . C_d + g_V . V (from the forward's saved C_d,
+//     V), the running prefix P_k = sum_{j<=k} w_j e_j, e_k = g_C . c_k +
+//     g_V . v_k and dL/dT_N = g_rgb . bg - g_alpha, Eq. 2/5/6 give
 //        dL/dsigma_k = delta [T_k e_k - (E - P_k) - T_N dL/dT_N],
 //        dL/dc_k = w_k g_C,  dL/dv_k = w_k g_V,
-//     (T_k: transmittance after sample k), which the trilinear weights
-//     scatter to the 8 corner voxels with float atomics.
+//     (T_k: transmittance after sample k).  Through the trilinear weights
+//     w_c(k) a corner voxel receives sum_k w_c(k) dL/dsigma_k (density) and
+//     g_C, g_V times A = sum_k w_c(k) w_k (colour, features).  Along one ray
+//     each cell coordinate is monotone, so the 8 corners of the current cell
+//     are kept as running (A, D) sums and a voxel is flushed to the gradient
+//     arrays (float atomics) once, when the ray's cell window leaves it.
 #include "march.h"
 #include "mlp.h"
 #include "snerg_launch.h"
@@ -21,16 +26,191 @@ namespace snerg {
 
 typedef float float4v __attribute__((ext_vector_type(4)));
 
-constexpr int kStageRow = 52;  // floats per ray in the LDS staging buffer
-constexpr int kBwdMaxWaves = 4;
+constexpr int kBwdWaves = 2;  // wavefronts per K1 workgroup
+// K1 staging row per ray (floats): gh1 | x (34) 1 0 | gh2 | h1 | go (3) 0 | h2
+constexpr int kSGh1 = 0, kSX = 16, kSGh2 = 52, kSH1 = 68, kSGo = 84, kSH2 = 88;
+constexpr int kStageRow = 105;
 
-// Adds val to the canonical gradient slot of padded corner (p + c) of block
-// (id at block coordinates b).  Corners outside the grid or in empty blocks
-// are structural zeros and get nothing.
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
+
+__device__ __forceinline__ void locate(const BackwardArgs& a, int64_t r, int& ci, int& px, int& py) {
+    ci = find_camera_by_ray(a.cams, a.n_cams, r);
+    const int64_t local = r - a.cams[ci].ray_offset;
+    py = int(local / a.cams[ci].W);
+    px = int(local - int64_t(py) * a.cams[ci].W);
+}
+
+// ------------------------------------------------------------------ K1: MLP
+
+__global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_backward(BackwardArgs a) {
+    __shared__ float stage[kBwdWaves][64][kStageRow];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    cfloat* W = as_const(a.mlp);
+    float* me = &stage[wave][lane][0];
+    const float* st = &stage[wave][0][0];
+    const int li = lane & 15, lk = lane >> 4;
+
+    float4v acc1[3] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+    float4v acc2 = {0.f, 0.f, 0.f, 0.f}, acc3 = {0.f, 0.f, 0.f, 0.f};
+    float db2 = 0.f, db3 = 0.f;  // lane j < 16 / < 3 holds the sum
+
+    const int64_t stride = int64_t(gridDim.x) * kBwdWaves * 64;
+    for (int64_t base = (int64_t(blockIdx.x) * kBwdWaves + wave) * 64; base < a.n_rays; base += stride) {
+        const int64_t i = base + lane;
+        const bool valid = i < a.n_rays;
+        float C[3] = {0.f, 0.f, 0.f}, V[4] = {0.f, 0.f, 0.f, 0.f}, d[3] = {0.f, 0.f, 1.f};
+        float gr[4] = {0.f, 0.f, 0.f, 0.f};
+        bool gate = false;
+        if (valid) {
+            const int64_t r = a.ray_ids ? a.ray_ids[i] : i;
+            int ci, px, py;
+            locate(a, r, ci, px, py);
+            int64_t o[3];
+            int32_t s[3];
+            ray_setup(a.cams[ci], a.grid.N, px, py, o, s, d);
+            const float4 a0 = reinterpret_cast<const float4*>(a.aux)[2 * i];
+            const float4 a1 = reinterpret_cast<const float4*>(a.aux)[2 * i + 1];
+            C[0] = a0.x; C[1] = a0.y; C[2] = a0.z; V[0] = a0.w;
+            V[1] = a1.x; V[2] = a1.y; V[3] = a1.z;
+            gate = a1.w >= 0.0f;
+            const float4 gg = reinterpret_cast<const float4*>(a.grad_rgba)[i];
+            gr[0] = gg.x; gr[1] = gg.y; gr[2] = gg.z; gr[3] = gg.w;
+        }
+        const bool use = valid && gate;
+
+        // forward, staging x, h1, h2 for the weight gradients
+        float x[kMlpIn];
+        encode_x(C, V, d, x);
+#pragma unroll
+        for (int q = 0; q < kMlpIn; ++q) me[kSX + q] = x[q];
+        me[kSX + 34] = use ? 1.0f : 0.0f;
+        me[kSX + 35] = 0.0f;
+        float h2[kMlpH];
+#pragma unroll
+        for (int k = 0; k < kMlpH; ++k) h2[k] = W[kOffB2 + k];
+#pragma nounroll
+        for (int j = 0; j < kMlpH; ++j) {
+            float t = W[kOffB1 + j];
+#pragma unroll
+            for (int q = 0; q < kMlpIn; ++q) t = fmaf(W[kOffW1 + j * kMlpIn + q], x[q], t);
+            const float h1j = fmaxf(t, 0.0f);
+            me[kSH1 + j] = use ? h1j : 0.0f;
+#pragma unroll
+            for (int k = 0; k < kMlpH; ++k) h2[k] = fmaf(W[kOffW2 + k * kMlpH + j], h1j, h2[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < kMlpH; ++k) {
+            h2[k] = fmaxf(h2[k], 0.0f);
+            me[kSH2 + k] = use ? h2[k] : 0.0f;
+        }
+        float go[kMlpOut];
+#pragma unroll
+        for (int j = 0; j < kMlpOut; ++j) {
+            float t = W[kOffB3 + j];
+#pragma unroll
+            for (int q = 0; q < kMlpH; ++q) t = fmaf(W[kOffW3 + j * kMlpH + q], h2[q], t);
+            const float R = sigmoid_f32(t);
+            go[j] = use ? gr[j] * R * (1.0f - R) : 0.0f;
+            me[kSGo + j] = go[j];
+        }
+        me[kSGo + 3] = 0.0f;
+        // backward through layers 3 and 2 (the ReLU masks come from h2, h1)
+#pragma unroll
+        for (int q = 0; q < kMlpH; ++q) {
+            float t = 0.f;
+#pragma unroll
+            for (int j = 0; j < kMlpOut; ++j) t = fmaf(W[kOffW3 + j * kMlpH + q], go[j], t);
+            h2[q] = h2[q] > 0.0f ? t : 0.0f;  // h2 now holds gh2
+            me[kSGh2 + q] = h2[q];
+        }
+        float gx[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma nounroll
+        for (int j = 0; j < kMlpH; ++j) {
+            float t = 0.f;
+#pragma unroll
+            for (int k = 0; k < kMlpH; ++k) t = fmaf(W[kOffW2 + k * kMlpH + j], h2[k], t);
+            const float gh1j = me[kSH1 + j] > 0.0f ? t : 0.0f;
+            me[kSGh1 + j] = gh1j;
+#pragma unroll
+            for (int q = 0; q < 7; ++q) gx[q] = fmaf(W[kOffW1 + j * kMlpIn + q], gh1j, gx[q]);
+        }
+        if (valid) {
+            float4* gcv = reinterpret_cast<float4*>(a.gcv) + 2 * i;
+            gcv[0] = make_float4(gr[0] + gx[0], gr[1] + gx[1], gr[2] + gx[2], gx[3]);
+            gcv[1] = make_float4(gx[4], gx[5], gx[6], 0.0f);
+        }
+#pragma unroll
+        for (int q = 0; q < kMlpH; ++q) {
+            const float sq = wave_sum(h2[q]);
+            if (lane == q) db2 += sq;
+        }
+#pragma unroll
+        for (int q = 0; q < kMlpOut; ++q) {
+            const float sq = wave_sum(go[q]);
+            if (lane == q) db3 += sq;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // dW = sum_r gA_r (x) act_r as 16x16x4 FP32 MFMAs: A = gradient rows
+        // (16 x 4 rays), B = activations (4 rays x 16); D lane l holds row
+        // 4(l/16) + v, column l % 16.
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            const float* rr = st + (4 * kk + lk) * kStageRow;
+            const float a1v = rr[kSGh1 + li];
+#pragma unroll
+            for (int nt = 0; nt < 3; ++nt) {
+                const int col = 16 * nt + li;
+                const float bv = col < 36 ? rr[kSX + col] : 0.0f;
+                acc1[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1v, bv, acc1[nt], 0, 0, 0);
+            }
+            acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(rr[kSGh2 + li], rr[kSH1 + li], acc2, 0, 0, 0);
+            acc3 = __builtin_amdgcn_mfma_f32_16x16x4f32(li < 4 ? rr[kSGo + li] : 0.0f, rr[kSH2 + li], acc3, 0, 0, 0);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+
+    // this wavefront's partial MLP gradient, in parameter order
+    float* out = a.g_mlp_partial + (int64_t(blockIdx.x) * kBwdWaves + wave) * kMlpParams;
+    const int lr = 4 * (lane >> 4);
+#pragma unroll
+    for (int nt = 0; nt < 3; ++nt) {
+        const int col = 16 * nt + li;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = lr + v;
+            if (col < kMlpIn) out[kOffW1 + row * kMlpIn + col] = acc1[nt][v];
+            else if (col == kMlpIn) out[kOffB1 + row] = acc1[nt][v];
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        out[kOffW2 + (lr + v) * kMlpH + li] = acc2[v];
+        if (lr + v < kMlpOut) out[kOffW3 + (lr + v) * kMlpH + li] = acc3[v];
+    }
+    if (lane < kMlpH) out[kOffB2 + lane] = db2;
+    if (lane < kMlpOut) out[kOffB3 + lane] = db3;
+}
+
+// --------------------------------------------------------------- K2: march
+
+// Canonical gradient slot of padded corner voxel (vx, vy, vz) (local
+// coordinates in [-1, B]) of the block with atlas id `id` at block
+// coordinates b.  Voxels outside the grid or in empty blocks are structural
+// zeros and have no slot (-1).
 __device__ __forceinline__ int64_t canonical_voxel(const GridArgs& g, int32_t id, const int32_t b[3],
                                                    int vx, int vy, int vz) {
     const int B = g.B;
     int32_t tid = id;
+    if (tid < 0 || tid >= g.n_blocks) return -1;
     if (vx < 0 || vy < 0 || vz < 0 || vx >= B || vy >= B || vz >= B) {
         const int nx = b[0] + (vx < 0 ? -1 : (vx >= B ? 1 : 0));
         const int ny = b[1] + (vy < 0 ? -1 : (vy >= B ? 1 : 0));
@@ -45,253 +225,154 @@ __device__ __forceinline__ int64_t canonical_voxel(const GridArgs& g, int32_t id
     return int64_t(tid) * B * B * B + (int64_t(vz) * B + vy) * B + vx;
 }
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
-    return v;
+// Running gradient sums for the 8 corner voxels of the ray's current cell.
+struct CellWindow {
+    int32_t c[3];  // padded cell coordinates
+    int32_t rank;  // block record, -1 when empty
+    int32_t id;    // atlas id of the block
+    int32_t b[3];  // block coordinates
+    float A[8], D[8];
+};
+
+template <bool FEAT>
+__device__ __forceinline__ void flush_corner(const BackwardArgs& a, const CellWindow& w, int c, const float gC[3],
+                                             const float gV[4]) {
+    const float A = w.A[c], D = w.D[c];
+    if (A == 0.0f && D == 0.0f) return;
+    const GridArgs& g = a.grid;
+    const int64_t vi = canonical_voxel(g, w.id, w.b, w.c[0] + (c & 1) - 1, w.c[1] + ((c >> 1) & 1) - 1,
+                                       w.c[2] + (c >> 2) - 1);
+    if (vi < 0) return;
+    unsafeAtomicAdd(a.grad_dens + vi, g.sigma_scale * D);
+    unsafeAtomicAdd(a.grad_rgb + 3 * vi + 0, A * gC[0]);
+    unsafeAtomicAdd(a.grad_rgb + 3 * vi + 1, A * gC[1]);
+    unsafeAtomicAdd(a.grad_rgb + 3 * vi + 2, A * gC[2]);
+    if (FEAT) {
+        unsafeAtomicAdd(a.grad_feat + 4 * vi + 0, A * gV[0]);
+        unsafeAtomicAdd(a.grad_feat + 4 * vi + 1, A * gV[1]);
+        unsafeAtomicAdd(a.grad_feat + 4 * vi + 2, A * gV[2]);
+        unsafeAtomicAdd(a.grad_feat + 4 * vi + 3, A * gV[3]);
+    }
 }
 
-template <int MLP>
-__global__ __launch_bounds__(256) void k_backward(BackwardArgs a) {
-    __shared__ float stage[kBwdMaxWaves][64][kStageRow];
+template <bool FEAT>
+__global__ __launch_bounds__(256) void k_march_backward(BackwardArgs a) {
     extern __shared__ uint2 s_occ[];
     for (int w = threadIdx.x; w < a.grid.n_words; w += blockDim.x) s_occ[w] = a.grid.occ[w];
     __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int wpg = blockDim.x >> 6;
     const GridArgs& g = a.grid;
     const float delta = 1.0f / float(g.N);
     const float kx = g.sigma_scale * delta;
-    cfloat* W = as_const(a.mlp);
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= a.n_rays) return;
+    const float4 a1 = reinterpret_cast<const float4*>(a.aux)[2 * i + 1];
+    if (!(a1.w >= 0.0f)) return;  // nothing was composited: no grid gradient
+    const float4 a0 = reinterpret_cast<const float4*>(a.aux)[2 * i];
+    const float4 gg = reinterpret_cast<const float4*>(a.grad_rgba)[i];
+    float gC[3] = {gg.x, gg.y, gg.z}, gV[4] = {0.f, 0.f, 0.f, 0.f};
+    if (FEAT) {
+        const float4 c0 = reinterpret_cast<const float4*>(a.gcv)[2 * i];
+        const float4 c1 = reinterpret_cast<const float4*>(a.gcv)[2 * i + 1];
+        gC[0] = c0.x; gC[1] = c0.y; gC[2] = c0.z;
+        gV[0] = c0.w; gV[1] = c1.x; gV[2] = c1.y; gV[3] = c1.z;
+    }
+    const float E = gC[0] * a0.x + gC[1] * a0.y + gC[2] * a0.z +
+                    (gV[0] * a0.w + gV[1] * a1.x + gV[2] * a1.y + gV[3] * a1.z);
+    const float gTN = gg.x * a.opts.bg[0] + gg.y * a.opts.bg[1] + gg.z * a.opts.bg[2] - gg.w;
+    const float tail = a1.w * gTN;
 
-    float4v acc1[3] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-    float4v acc2 = {0.f, 0.f, 0.f, 0.f}, acc3 = {0.f, 0.f, 0.f, 0.f};
-    float db2 = 0.f, db3 = 0.f;  // lane j < 16 / < 3 holds the sum
+    const int64_t r = a.ray_ids ? a.ray_ids[i] : i;
+    int ci, px, py;
+    locate(a, r, ci, px, py);
+    int64_t o[3];
+    int32_t s[3];
+    float d[3];
+    ray_setup(a.cams[ci], g.N, px, py, o, s, d);
 
-    const int64_t stride = int64_t(gridDim.x) * wpg * 64;
-    for (int64_t base = (int64_t(blockIdx.x) * wpg + wave) * 64; base < a.n_rays; base += stride) {
-        const int64_t i = base + lane;
-        const bool valid = i < a.n_rays;
-        int ci = 0, px = 0, py = 0;
-        if (valid) {
-            const int64_t r = a.ray_ids ? a.ray_ids[i] : i;
-            ci = find_camera_by_ray(a.cams, a.n_cams, r);
-            const int64_t local = r - a.cams[ci].ray_offset;
-            py = int(local / a.cams[ci].W);
-            px = int(local - int64_t(py) * a.cams[ci].W);
-        }
-        int64_t o[3] = {0, 0, 0};
-        int32_t s[3] = {0, 0, 0};
-        float d[3] = {0.f, 0.f, 1.f};
-        float C[3] = {0.f, 0.f, 0.f}, V[4] = {0.f, 0.f, 0.f, 0.f}, TN = 1.0f;
-        float gr[4] = {0.f, 0.f, 0.f, 0.f};
-        bool gate = false;
-        if (valid) {
-            ray_setup(a.cams[ci], g.N, px, py, o, s, d);
-            const float4 a0 = reinterpret_cast<const float4*>(a.aux)[2 * i];
-            const float4 a1 = reinterpret_cast<const float4*>(a.aux)[2 * i + 1];
-            C[0] = a0.x; C[1] = a0.y; C[2] = a0.z; V[0] = a0.w;
-            V[1] = a1.x; V[2] = a1.y; V[3] = a1.z;
-            gate = a1.w >= 0.0f;
-            TN = gate ? a1.w : 1.0f;
-            const float4 gg = reinterpret_cast<const float4*>(a.grad_rgba)[i];
-            gr[0] = gg.x; gr[1] = gg.y; gr[2] = gg.z; gr[3] = gg.w;
-        }
-        float gC[3] = {gr[0], gr[1], gr[2]};
-        float gV[4] = {0.f, 0.f, 0.f, 0.f};
-
-        if (MLP != kMlpOff) {
-            const bool use = valid && gate && a.opts.mlp_on;
-            float x[kMlpIn];
-            encode_x(C, V, d, x);
-            float h1[kMlpH], h2[kMlpH], go[kMlpOut], gh1[kMlpH], gh2[kMlpH];
+    CellWindow win;
+    win.rank = -1;
+    win.id = 0;
+    win.c[0] = win.c[1] = win.c[2] = 0;
+    win.b[0] = win.b[1] = win.b[2] = 0;
 #pragma unroll
-            for (int j = 0; j < kMlpH; ++j) {
-                float t = W[kOffB1 + j];
+    for (int c = 0; c < 8; ++c) win.A[c] = win.D[c] = 0.0f;
+    float T = 1.0f, Pk = 0.0f;
+    const float t_stop = a.opts.t_stop;
+    const bool early = a.opts.early_stop != 0;
+    march_ray(
+        g, s_occ, o, s, [](int32_t, bool) {}, [](int32_t) {},
+        [&](int64_t, int32_t rk, const uint8_t* vox, const int32_t p[3], const int32_t fr[3]) {
+            Sample smp;
+            gather_f32(vox, g.Bp, p, fr, smp);
+            if (!smp.active) return false;
+            const float e = __expf(-smp.sigma_raw * kx);
+            const float w = T * (1.0f - e);
+            const float ek = gC[0] * smp.rgb[0] + gC[1] * smp.rgb[1] + gC[2] * smp.rgb[2] +
+                             (gV[0] * smp.feat[0] + gV[1] * smp.feat[1] + gV[2] * smp.feat[2] +
+                              gV[3] * smp.feat[3]);
+            Pk += w * ek;
+            T *= e;
+            const float gsig = delta * (T * ek - (E - Pk) - tail);
+            // Slide the corner window to this sample's cell: corners on a
+            // trailing face (or all of them after a jump) are flushed once,
+            // the survivors shift to their new corner index.
+            const bool jump = win.rank != rk || abs(p[0] - win.c[0]) > 1 || abs(p[1] - win.c[1]) > 1 ||
+                              abs(p[2] - win.c[2]) > 1;
+            int dd[3] = {p[0] - win.c[0], p[1] - win.c[1], p[2] - win.c[2]};
+            uint32_t leave = 0;
+            if (jump) {
+                leave = win.rank >= 0 ? 0xFFu : 0u;
+            } else {
 #pragma unroll
-                for (int q = 0; q < kMlpIn; ++q) t = fmaf(W[kOffW1 + j * kMlpIn + q], x[q], t);
-                h1[j] = fmaxf(t, 0.0f);
-            }
-#pragma unroll
-            for (int j = 0; j < kMlpH; ++j) {
-                float t = W[kOffB2 + j];
-#pragma unroll
-                for (int q = 0; q < kMlpH; ++q) t = fmaf(W[kOffW2 + j * kMlpH + q], h1[q], t);
-                h2[j] = fmaxf(t, 0.0f);
-            }
-#pragma unroll
-            for (int j = 0; j < kMlpOut; ++j) {
-                float t = W[kOffB3 + j];
-#pragma unroll
-                for (int q = 0; q < kMlpH; ++q) t = fmaf(W[kOffW3 + j * kMlpH + q], h2[q], t);
-                const float R = sigmoid_f32(t);
-                go[j] = use ? gr[j] * R * (1.0f - R) : 0.0f;
-            }
-#pragma unroll
-            for (int q = 0; q < kMlpH; ++q) {
-                float t = 0.f;
-#pragma unroll
-                for (int j = 0; j < kMlpOut; ++j) t = fmaf(W[kOffW3 + j * kMlpH + q], go[j], t);
-                gh2[q] = h2[q] > 0.0f ? t : 0.0f;
-            }
-#pragma unroll
-            for (int q = 0; q < kMlpH; ++q) {
-                float t = 0.f;
-#pragma unroll
-                for (int j = 0; j < kMlpH; ++j) t = fmaf(W[kOffW2 + j * kMlpH + q], gh2[j], t);
-                gh1[q] = h1[q] > 0.0f ? t : 0.0f;
-            }
-#pragma unroll
-            for (int q = 0; q < 7; ++q) {
-                float t = 0.f;
-#pragma unroll
-                for (int j = 0; j < kMlpH; ++j) t = fmaf(W[kOffW1 + j * kMlpIn + q], gh1[j], t);
-                if (q < 3) gC[q] += t; else gV[q - 3] = t;
-            }
-
-            // Weight gradients: dW = sum_r gA_r (x) act_r as 16x16x4 FP32 MFMAs,
-            // A = gradient rows (16 x 4 rays), B = activations (4 rays x 16).
-            float* st = &stage[wave][0][0];
-            float* me = &stage[wave][lane][0];
-            // phase 1: gh1 (16) | x (34) | 1 (bias column) | 0
-#pragma unroll
-            for (int q = 0; q < kMlpH; ++q) me[q] = gh1[q];
-#pragma unroll
-            for (int q = 0; q < kMlpIn; ++q) me[16 + q] = x[q];
-            me[16 + 34] = use ? 1.0f : 0.0f;
-            me[16 + 35] = 0.0f;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const int li = lane & 15, lk = lane >> 4;
-#pragma unroll
-            for (int kk = 0; kk < 16; ++kk) {
-                const float* rr = st + (4 * kk + lk) * kStageRow;
-                const float av = rr[li];
-#pragma unroll
-                for (int nt = 0; nt < 3; ++nt) {
-                    const int col = 16 * nt + li;
-                    const float bv = col < 36 ? rr[16 + col] : 0.0f;
-                    acc1[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc1[nt], 0, 0, 0);
+                for (int ax = 0; ax < 3; ++ax) {
+                    // corners with bit ax clear: 0x55, 0x33, 0x0F for ax = 0, 1, 2
+                    const uint32_t clear = ax == 0 ? 0x55u : (ax == 1 ? 0x33u : 0x0Fu);
+                    if (dd[ax] > 0) leave |= clear;
+                    if (dd[ax] < 0) leave |= ~clear & 0xFFu;
                 }
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            // phase 2: gh2 (16) | h1 (16) | go (3) | h2 (16)
 #pragma unroll
-            for (int q = 0; q < kMlpH; ++q) me[q] = gh2[q];
+            for (int c = 0; c < 8; ++c)
+                if ((leave >> c) & 1u) flush_corner<FEAT>(a, win, c, gC, gV);
+            if (jump) {
 #pragma unroll
-            for (int q = 0; q < kMlpH; ++q) me[16 + q] = use ? h1[q] : 0.0f;
+                for (int c = 0; c < 8; ++c) win.A[c] = win.D[c] = 0.0f;
+                win.rank = rk;
+                win.id = g.rank_id[rk];
+                const int32_t lin = g.rank_lin[rk];
+                win.b[0] = lin % g.G;
+                win.b[1] = (lin / g.G) % g.G;
+                win.b[2] = lin / (g.G * g.G);
+                win.c[0] = p[0]; win.c[1] = p[1]; win.c[2] = p[2];
+            } else {
 #pragma unroll
-            for (int q = 0; q < kMlpOut; ++q) me[32 + q] = go[q];
-#pragma unroll
-            for (int q = 0; q < kMlpH; ++q) me[35 + q] = use ? h2[q] : 0.0f;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-            for (int kk = 0; kk < 16; ++kk) {
-                const float* rr = st + (4 * kk + lk) * kStageRow;
-                acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(rr[li], rr[16 + li], acc2, 0, 0, 0);
-                const float a3 = li < 3 ? rr[32 + li] : 0.0f;
-                acc3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a3, rr[35 + li], acc3, 0, 0, 0);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-            for (int q = 0; q < kMlpH; ++q) {
-                const float sq = wave_sum(gh2[q]);
-                if (lane == q) db2 += sq;
-            }
-#pragma unroll
-            for (int q = 0; q < kMlpOut; ++q) {
-                const float sq = wave_sum(go[q]);
-                if (lane == q) db3 += sq;
-            }
-            if (!a.opts.mlp_on) {
-                gC[0] = gr[0]; gC[1] = gr[1]; gC[2] = gr[2];
-                gV[0] = gV[1] = gV[2] = gV[3] = 0.0f;
-            }
-        }
-
-        if (valid && gate) {
-            const float E = gC[0] * C[0] + gC[1] * C[1] + gC[2] * C[2] +
-                            (gV[0] * V[0] + gV[1] * V[1] + gV[2] * V[2] + gV[3] * V[3]);
-            const float gTN = gr[0] * a.opts.bg[0] + gr[1] * a.opts.bg[1] + gr[2] * a.opts.bg[2] - gr[3];
-            const float tail = TN * gTN;
-            float T = 1.0f, Pk = 0.0f;
-            const float t_stop = a.opts.t_stop;
-            const bool early = a.opts.early_stop != 0;
-            march_ray(
-                g, s_occ, o, s, [](int32_t, bool) {}, [](int32_t) {},
-                [&](int64_t, int32_t rk, const uint8_t* vox, const int32_t p[3], const int32_t fr[3]) {
-                    Sample smp;
-                    gather_f32(vox, g.Bp, p, fr, smp);
-                    if (!smp.active) return false;
-                    const float x = smp.sigma_raw * kx;
-                    const float e = __expf(-x);
-                    const float alpha = 1.0f - e;
-                    const float w = T * alpha;
-                    const float ek = gC[0] * smp.rgb[0] + gC[1] * smp.rgb[1] + gC[2] * smp.rgb[2] +
-                                     (gV[0] * smp.feat[0] + gV[1] * smp.feat[1] + gV[2] * smp.feat[2] +
-                                      gV[3] * smp.feat[3]);
-                    Pk += w * ek;
-                    T *= e;
-                    const float gsig = delta * (T * ek - (E - Pk) - tail);
-                    // scatter through the trilinear weights
-                    const int32_t lin = g.rank_lin[rk];
-                    const int32_t id = g.rank_id[rk];
-                    const int32_t b[3] = {lin % g.G, (lin / g.G) % g.G, lin / (g.G * g.G)};
-                    float wc[8];
-                    corner_weights(fr, wc);
-                    const float gd = g.sigma_scale * gsig;
+                for (int ax = 0; ax < 3; ++ax) {
+                    const int bit = 1 << ax;
 #pragma unroll
                     for (int c = 0; c < 8; ++c) {
-                        if (!corner_live(c, fr)) continue;
-                        const int64_t vi = canonical_voxel(g, id, b, p[0] + (c & 1) - 1,
-                                                           p[1] + ((c >> 1) & 1) - 1, p[2] + (c >> 2) - 1);
-                        if (vi < 0) continue;
-                        const float ww = wc[c] * w;
-                        unsafeAtomicAdd(a.grad_dens + vi, wc[c] * gd);
-                        unsafeAtomicAdd(a.grad_rgb + 3 * vi + 0, ww * gC[0]);
-                        unsafeAtomicAdd(a.grad_rgb + 3 * vi + 1, ww * gC[1]);
-                        unsafeAtomicAdd(a.grad_rgb + 3 * vi + 2, ww * gC[2]);
-                        if (MLP != kMlpOff) {
-                            unsafeAtomicAdd(a.grad_feat + 4 * vi + 0, ww * gV[0]);
-                            unsafeAtomicAdd(a.grad_feat + 4 * vi + 1, ww * gV[1]);
-                            unsafeAtomicAdd(a.grad_feat + 4 * vi + 2, ww * gV[2]);
-                            unsafeAtomicAdd(a.grad_feat + 4 * vi + 3, ww * gV[3]);
-                        }
+                        if (c & bit) continue;
+                        const int c1 = c | bit;
+                        const float a0v = win.A[c], d0v = win.D[c], a1v = win.A[c1], d1v = win.D[c1];
+                        win.A[c] = dd[ax] > 0 ? a1v : (dd[ax] < 0 ? 0.0f : a0v);
+                        win.D[c] = dd[ax] > 0 ? d1v : (dd[ax] < 0 ? 0.0f : d0v);
+                        win.A[c1] = dd[ax] < 0 ? a0v : (dd[ax] > 0 ? 0.0f : a1v);
+                        win.D[c1] = dd[ax] < 0 ? d0v : (dd[ax] > 0 ? 0.0f : d1v);
                     }
-                    return early && T < t_stop;
-                });
-        }
-    }
-
-    if (MLP != kMlpOff) {
-        // this wavefront's partial MLP gradient, in parameter order
-        float* out = a.g_mlp_partial + (int64_t(blockIdx.x) * wpg + wave) * kMlpParams;
-        const int li = lane & 15, lr = 4 * (lane >> 4);
-#pragma unroll
-        for (int nt = 0; nt < 3; ++nt) {
-            const int col = 16 * nt + li;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = lr + v;
-                if (col < kMlpIn) out[kOffW1 + row * kMlpIn + col] = acc1[nt][v];
-                else if (col == kMlpIn) out[kOffB1 + row] = acc1[nt][v];
+                    win.c[ax] += dd[ax];
+                }
             }
-        }
+            float wc[8];
+            corner_weights(fr, wc);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            out[kOffW2 + (lr + v) * kMlpH + li] = acc2[v];
-            if (lr + v < kMlpOut) out[kOffW3 + (lr + v) * kMlpH + li] = acc3[v];
-        }
-        if (lane < kMlpH) out[kOffB2 + lane] = db2;
-        if (lane < kMlpOut) out[kOffB3 + lane] = db3;
+            for (int c = 0; c < 8; ++c) {
+                win.A[c] = fmaf(wc[c], w, win.A[c]);
+                win.D[c] = fmaf(wc[c], gsig, win.D[c]);
+            }
+            return early && T < t_stop;
+        });
+    if (win.rank >= 0) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) flush_corner<FEAT>(a, win, c, gC, gV);
     }
 }
 
@@ -303,13 +384,21 @@ __global__ void k_reduce_rows(const float* __restrict__ partial, int rows, float
     out[j] = s;
 }
 
+int backward_partial_rows(int n_groups) { return n_groups * kBwdWaves; }
+
 hipError_t launch_backward(const BackwardArgs& a, int n_groups, hipStream_t s) {
-    if (n_groups <= 0) return hipSuccess;
+    if (a.n_rays <= 0) return hipSuccess;
+    hipError_t e;
+    if (a.mlp_mode != kMlpOff) {
+        hipLaunchKernelGGL(k_mlp_backward, dim3(n_groups), dim3(64 * kBwdWaves), 0, s, a);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     const size_t lds = size_t(a.grid.n_words) * sizeof(uint2);
-    if (a.mlp_mode == kMlpOff)
-        hipLaunchKernelGGL(k_backward<kMlpOff>, dim3(n_groups), dim3(64 * kBwdMaxWaves), lds, s, a);
+    const unsigned blocks = unsigned((a.n_rays + 255) / 256);
+    if (a.mlp_mode != kMlpOff)
+        hipLaunchKernelGGL(k_march_backward<true>, dim3(blocks), dim3(256), lds, s, a);
     else
-        hipLaunchKernelGGL(k_backward<kMlpF32>, dim3(n_groups), dim3(64 * kBwdMaxWaves), lds, s, a);
+        hipLaunchKernelGGL(k_march_backward<false>, dim3(blocks), dim3(256), lds, s, a);
     return hipGetLastError();
 }
 

@@ -49,7 +49,8 @@ struct BackwardArgs {
     int64_t n_rays;
     const float* aux;
     const float* grad_rgba;
-    float* g_mlp_partial;  // [n_groups][883]
+    float* g_mlp_partial;  // [rows][883], rows = backward_partial_rows(n_groups)
+    float* gcv;            // [n_rays][8]: g_C (3), g_V (4) per ray from the MLP backward
     float* grad_dens;
     float* grad_rgb;
     float* grad_feat;
@@ -66,6 +67,7 @@ hipError_t launch_render(const RenderArgs& a, int vt, int mlp_mode, int waves_pe
                          int n_groups, hipStream_t s);
 hipError_t launch_trace(const RenderArgs& a, int vt, hipStream_t s);
 hipError_t launch_backward(const BackwardArgs& a, int n_groups, hipStream_t s);
+int backward_partial_rows(int n_groups);
 hipError_t launch_reduce_mlp(const float* partial, int n_groups, float* out, hipStream_t s);
 
 }  // namespace snerg
