@@ -182,7 +182,8 @@ int snerg_render(snerg_handle *h, const snerg_grid *grid, const float *mlp, cons
  * cameras and options.  grad_rgba: device [n_rays][4].  Outputs (device,
  * overwritten, not accumulated): grad_mlp [883], grad_dens, grad_rgb,
  * grad_feat in canonical atlas layout.  Gradient sums use float32 atomics,
- * so their rounding depends on scheduling.
+ * so their rounding depends on scheduling.  With SNERG_FLAG_MLP_FP16 the MLP
+ * backward runs on FP16 MFMA tiles with FP32 accumulation (as the forward).
  */
 int snerg_render_backward(snerg_handle *h, const snerg_grid *grid, const float *mlp,
                           const snerg_camera *cams, int32_t n_cams, const int64_t *ray_ids,

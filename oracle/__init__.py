@@ -69,7 +69,7 @@ def _load():
                                    ctypes.c_int32]
         lib.orc_trace_visits.argtypes = [P, P, ctypes.c_int32, P, ctypes.c_int64, P, ctypes.c_int32,
                                          P, P, ctypes.c_int32]
-        lib.orc_render_grad.argtypes = [P, P, P, ctypes.c_int32, P, ctypes.c_int64, P, P, P, P, P, P]
+        lib.orc_render_grad.argtypes = [P, P, P, ctypes.c_int32, P, ctypes.c_int64, P, P, P, P, P, P, P]
         for f in (lib.orc_ray_setup, lib.orc_sample, lib.orc_composite, lib.orc_encode, lib.orc_mlp,
                   lib.orc_render, lib.orc_trace_visits, lib.orc_render_grad):
             f.restype = ctypes.c_int
@@ -232,9 +232,11 @@ def trace_visits(og: OracleGrid, cams, ray_ids=None, early_stop=False, t_stop=DE
 
 
 def render_grad(og: OracleGrid, mlp, cams, g_rgba, ray_ids=None, bg=(1.0, 1.0, 1.0),
-                t_stop=DEFAULT_T_STOP, early_stop=True, mlp_on=True):
+                t_stop=DEFAULT_T_STOP, early_stop=True, mlp_on=True, g_cv=None):
     """Gradient of sum(g_rgba * rgba) w.r.t. the 883 MLP parameters and the
-    grid values (float grids only).  Returns (g_mlp, g_dens, g_rgb, g_feat)."""
+    grid values (float grids only).  Returns (g_mlp, g_dens, g_rgb, g_feat).
+    g_cv [n, 7] (optional) supplies each ray's dL/dC_d, dL/dV in place of the
+    MLP backward (the MLP gradient is then zero)."""
     lib = _load()
     assert og.dtype != U8, "gradients need a float (shadow) grid"
     ids, n = _ids(ray_ids, cams)
@@ -246,7 +248,8 @@ def render_grad(og: OracleGrid, mlp, cams, g_rgba, ray_ids=None, bg=(1.0, 1.0, 1
     gd = np.zeros(og.arrays[0].shape, np.float64)
     gr = np.zeros(og.arrays[1].shape, np.float64)
     gf = np.zeros(og.arrays[2].shape, np.float64)
+    cv = np.ascontiguousarray(g_cv, np.float64).reshape(n, 7) if g_cv is not None else None
     _check(lib.orc_render_grad(ctypes.byref(og.struct), _ptr(p), c, len(cams), _ptr(ids), n,
                                ctypes.byref(o), g.ctypes.data, gm.ctypes.data, gd.ctypes.data,
-                               gr.ctypes.data, gf.ctypes.data), "render_grad")
+                               gr.ctypes.data, gf.ctypes.data, _ptr(cv)), "render_grad")
     return gm, gd, gr, gf

@@ -569,11 +569,14 @@ int orc_trace_visits(const orc_grid *g, const orc_camera *cams, int32_t n_cams,
  * Plain reverse-mode: each ray's composited samples are stored during the
  * forward march, then the MLP, the compositing recurrence and the
  * trilinear weights are differentiated in reverse order.  Single threaded.
+ * With g_cv (nullable, [n][7]) the MLP is not differentiated: its rows give
+ * each ray's dL/dC_d (3) and dL/dV (4) directly (to check a reduced
+ * precision MLP backward against this FP64 march backward).
  */
 int orc_render_grad(const orc_grid *g, const double *mlp, const orc_camera *cams, int32_t n_cams,
                     const int64_t *ray_ids, int64_t n_rays, const orc_opts *op,
                     const double *g_rgba, double *g_mlp, double *g_dens, double *g_rgb,
-                    double *g_feat)
+                    double *g_feat, const double *g_cv)
 {
     if (check_grid(g) || g->dtype == ORC_U8 || !cams || n_cams <= 0 || !op || !g_rgba) return ORC_EINVAL;
     if (!g_mlp || !g_dens || !g_rgb || !g_feat || (!mlp && op->mlp_on)) return ORC_EINVAL;
@@ -599,7 +602,10 @@ int orc_render_grad(const orc_grid *g, const double *mlp, const orc_camera *cams
         /* rgb = C + T bg + R, alpha = 1 - T */
         double gT = gr[0] * op->bg[0] + gr[1] * op->bg[1] + gr[2] * op->bg[2] - gr[3];
 
-        if (res.aux[8] != 0.0 && op->mlp_on && mlp) {
+        if (g_cv) {
+            for (int ch = 0; ch < 3; ++ch) gC[ch] = g_cv[7 * i + ch];
+            for (int ch = 0; ch < 4; ++ch) gV[ch] = g_cv[7 * i + 3 + ch];
+        } else if (res.aux[8] != 0.0 && op->mlp_on && mlp) {
             double x[MLP_IN];
             orc_encode(res.aux, res.aux + 3, res.d, x);
             mlp_acts a;

@@ -435,7 +435,6 @@ int snerg_render_backward(snerg_handle* h, const snerg_grid* grid, const float* 
     int rc = common_render_checks(grid, mlp, true, cams, n_cams, ray_ids, n_rays, opts, &total);
     if (rc) return rc;
     if (grid->dtype != SNERG_F32) return fail(SNERG_ERR_UNSUPPORTED, "the backward pass needs a SNERG_F32 grid");
-    if (opts->flags & SNERG_FLAG_MLP_FP16) return fail(SNERG_ERR_UNSUPPORTED, "FP16 MLP backward is not available");
     if (!aux || !grad_rgba) return fail(SNERG_ERR_INVALID_ARG, "aux/grad_rgba is NULL");
     if (!grad_mlp || !grad_dens || !grad_rgb || !grad_feat) return fail(SNERG_ERR_INVALID_ARG, "a gradient output is NULL");
     if (!h) return fail(SNERG_ERR_INVALID_ARG, "handle is NULL");
@@ -444,7 +443,7 @@ int snerg_render_backward(snerg_handle* h, const snerg_grid* grid, const float* 
     const int64_t nv = int64_t(grid->n_blocks) * B3;
     const int64_t want = (n_rays + 127) / 128;
     const int n_groups = int(std::max<int64_t>(1, std::min<int64_t>(want, int64_t(h->n_cu) * 8)));
-    const int mlp_mode = opts->mlp_on ? kMlpF32 : kMlpOff;
+    const int mlp_mode = !opts->mlp_on ? kMlpOff : ((opts->flags & SNERG_FLAG_MLP_FP16) ? kMlpF16 : kMlpF32);
     const int rows = backward_partial_rows(n_groups);
     if (mlp_mode != kMlpOff) {
         rc = ensure_buffer(&h->d_partial, &h->partial_cap, size_t(rows) * kMlpParams);

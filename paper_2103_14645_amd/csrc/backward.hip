@@ -46,8 +46,108 @@ __device__ __forceinline__ void locate(const BackwardArgs& a, int64_t r, int& ci
 
 // ------------------------------------------------------------------ K1: MLP
 
+// A-operand fragment of the transpose of a row-major [rows][cols] matrix M
+// (a 16x16 tile of M^T): lane l holds M^T[l%16][4(l/16) + j] = M[4(l/16) + j][l%16].
+__device__ __forceinline__ half4_t a_frag_t(cfloat* M, int rows, int cols, int lane) {
+    const int c = lane & 15;
+    const int r = 4 * (lane >> 4);
+    half4_t v;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = (r + j < rows && c < cols) ? _Float16(M[(r + j) * cols + c]) : _Float16(0.0f);
+    return v;
+}
+
+__device__ __forceinline__ half4_t to_half4(float4_t v) {
+    half4_t h;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) h[j] = _Float16(v[j]);
+    return h;
+}
+
+// The MLP chain of 64 rays on FP16 MFMA tiles.  xs: the rays' inputs
+// ([64][kXRow] halves), gsm: per ray g_rgb and the gate, stage: per-ray
+// rows that receive h1, h2, go, gh2, gh1 (float).  Tile layouts (16x16x16):
+// A lane l = [m = l%16][k = 4(l/16)+j], B lane l = [k = 4(l/16)+j][n = l%16],
+// D lane l = [m = 4(l/16)+v][n = l%16]; hidden units are rows, rays columns,
+// so every D tile (after its element-wise step) is the next B operand.
+__device__ __forceinline__ void mlp_backward_f16_wave(const BackwardArgs& a, cfloat* W, const _Float16* xs,
+                                                      const float* gsm, float* stage, int64_t base, int lane) {
+    half4_t w1[3];
+#pragma unroll
+    for (int kc = 0; kc < 3; ++kc) w1[kc] = a_frag(W + kOffW1, kMlpH, kMlpIn, 0, 16 * kc, lane);
+    const half4_t w2 = a_frag(W + kOffW2, kMlpH, kMlpH, 0, 0, lane);
+    const half4_t w3 = a_frag(W + kOffW3, kMlpOut, kMlpH, 0, 0, lane);
+    const half4_t w3t = a_frag_t(W + kOffW3, kMlpOut, kMlpH, lane);
+    const half4_t w2t = a_frag_t(W + kOffW2, kMlpH, kMlpH, lane);
+    const half4_t w1t = a_frag_t(W + kOffW1, kMlpH, kMlpIn, lane);  // input rows 0..15
+    const float4_t bb1 = bias_frag(W + kOffB1, kMlpH, lane);
+    const float4_t bb2 = bias_frag(W + kOffB2, kMlpH, lane);
+    const float4_t bb3 = bias_frag(W + kOffB3, kMlpOut, lane);
+    const float4_t zero = {0.f, 0.f, 0.f, 0.f};
+    const int n = lane & 15, rq = 4 * (lane >> 4);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const int ray = 16 * g + n;  // this lane's column
+        const _Float16* row = xs + ray * kXRow + rq;
+        float4_t h1 = bb1;
+#pragma unroll
+        for (int kc = 0; kc < 3; ++kc)
+            h1 = __builtin_amdgcn_mfma_f32_16x16x16f16(w1[kc], *reinterpret_cast<const half4_t*>(row + 16 * kc), h1,
+                                                       0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) h1[v] = fmaxf(h1[v], 0.0f);
+        float4_t h2 = __builtin_amdgcn_mfma_f32_16x16x16f16(w2, to_half4(h1), bb2, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) h2[v] = fmaxf(h2[v], 0.0f);
+        const float4_t o = __builtin_amdgcn_mfma_f32_16x16x16f16(w3, to_half4(h2), bb3, 0, 0, 0);
+        const float use = gsm[ray * 4 + 3];
+        float4_t go = zero;
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            if (lane < 16) {
+                const float R = sigmoid_f32(o[v]);
+                go[v] = use * gsm[ray * 4 + v] * R * (1.0f - R);
+            }
+        }
+        float4_t gh2 = __builtin_amdgcn_mfma_f32_16x16x16f16(w3t, to_half4(go), zero, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) gh2[v] = h2[v] > 0.0f ? gh2[v] : 0.0f;
+        float4_t gh1 = __builtin_amdgcn_mfma_f32_16x16x16f16(w2t, to_half4(gh2), zero, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) gh1[v] = h1[v] > 0.0f ? gh1[v] : 0.0f;
+        const float4_t gx = __builtin_amdgcn_mfma_f32_16x16x16f16(w1t, to_half4(gh1), zero, 0, 0, 0);
+        float* sr = stage + ray * kStageRow;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            sr[kSH1 + rq + v] = use * h1[v];
+            sr[kSH2 + rq + v] = use * h2[v];
+            sr[kSGh2 + rq + v] = gh2[v];
+            sr[kSGh1 + rq + v] = gh1[v];
+            if (lane < 16) sr[kSGo + v] = go[v];
+        }
+        // g_C = g_rgb + gx[0:3], g_V = gx[3:7]: rows 0..3 sit in lanes 0..15,
+        // rows 4..7 in lanes 16..31
+        const int64_t i = base + ray;
+        if (i < a.n_rays && lane < 32) {
+            float4* gcv = reinterpret_cast<float4*>(a.gcv) + 2 * i;
+            if (lane < 16)
+                gcv[0] = make_float4(gsm[ray * 4 + 0] + gx[0], gsm[ray * 4 + 1] + gx[1], gsm[ray * 4 + 2] + gx[2], gx[3]);
+            else
+                gcv[1] = make_float4(gx[0], gx[1], gx[2], 0.0f);
+        }
+    }
+}
+
+// F16: the MLP chain (forward and backward through the three layers) runs as
+// v_mfma_f32_16x16x16_f16 tiles over the wavefront's 64 rays (FP16 operands,
+// FP32 accumulation); the per-ray activations and gradients land in the same
+// staging rows as in the FP32 path, and the weight gradients are summed by
+// the same FP32 MFMA outer products.
+template <bool F16>
 __global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_backward(BackwardArgs a) {
     __shared__ float stage[kBwdWaves][64][kStageRow];
+    __shared__ _Float16 xs[F16 ? kBwdWaves : 1][64][kXRow];
+    __shared__ float gsm[F16 ? kBwdWaves : 1][64][4];  // g_rgb (3), gate
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     cfloat* W = as_const(a.mlp);
@@ -90,6 +190,32 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_backward(BackwardArgs a)
         for (int q = 0; q < kMlpIn; ++q) me[kSX + q] = x[q];
         me[kSX + 34] = use ? 1.0f : 0.0f;
         me[kSX + 35] = 0.0f;
+        if (F16) {
+#pragma unroll
+            for (int q = 0; q < kXPad; ++q) xs[F16 ? wave : 0][lane][q] = _Float16(q < kMlpIn ? x[q] : 0.0f);
+            gsm[F16 ? wave : 0][lane][0] = gr[0];
+            gsm[F16 ? wave : 0][lane][1] = gr[1];
+            gsm[F16 ? wave : 0][lane][2] = gr[2];
+            gsm[F16 ? wave : 0][lane][3] = use ? 1.0f : 0.0f;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            mlp_backward_f16_wave(a, W, &xs[F16 ? wave : 0][0][0], &gsm[F16 ? wave : 0][0][0],
+                                  &stage[wave][0][0], base, lane);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (lane < kMlpH) {
+                float t = 0.f;
+                for (int r = 0; r < 64; ++r) t += st[r * kStageRow + kSGh2 + lane];
+                db2 += t;
+            }
+            if (lane < kMlpOut) {
+                float t = 0.f;
+                for (int r = 0; r < 64; ++r) t += st[r * kStageRow + kSGo + lane];
+                db3 += t;
+            }
+        } else {
         float h2[kMlpH];
 #pragma unroll
         for (int k = 0; k < kMlpH; ++k) h2[k] = W[kOffB2 + k];
@@ -153,6 +279,7 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_backward(BackwardArgs a)
         for (int q = 0; q < kMlpOut; ++q) {
             const float sq = wave_sum(go[q]);
             if (lane == q) db3 += sq;
+        }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -389,8 +516,11 @@ int backward_partial_rows(int n_groups) { return n_groups * kBwdWaves; }
 hipError_t launch_backward(const BackwardArgs& a, int n_groups, hipStream_t s) {
     if (a.n_rays <= 0) return hipSuccess;
     hipError_t e;
-    if (a.mlp_mode != kMlpOff) {
-        hipLaunchKernelGGL(k_mlp_backward, dim3(n_groups), dim3(64 * kBwdWaves), 0, s, a);
+    if (a.mlp_mode == kMlpF16) {
+        hipLaunchKernelGGL(k_mlp_backward<true>, dim3(n_groups), dim3(64 * kBwdWaves), 0, s, a);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else if (a.mlp_mode == kMlpF32) {
+        hipLaunchKernelGGL(k_mlp_backward<false>, dim3(n_groups), dim3(64 * kBwdWaves), 0, s, a);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     const size_t lds = size_t(a.grid.n_words) * sizeof(uint2);

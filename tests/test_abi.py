@@ -138,7 +138,7 @@ def test_backward_trace_pack_autotune_validation():
     assert bw(u8) == S.SNERG_ERR_UNSUPPORTED
     assert bw(f32, gm=None) == S.SNERG_ERR_INVALID_ARG
     assert bw(f32) == S.SNERG_ERR_INVALID_ARG and "handle" in last_error()
-    assert bw(f32, o=S.make_opts(fp16=True)) == S.SNERG_ERR_UNSUPPORTED
+    assert bw(f32, o=S.make_opts(fp16=True)) == S.SNERG_ERR_INVALID_ARG and "handle" in last_error()
     tr = lambda mv, vis: lib.snerg_trace_visits(None, ctypes.byref(u8), cams, 1, None, 32, ctypes.byref(opts),
                                                 mv, vis, FAKE, None, None)
     assert tr(-1, FAKE) == S.SNERG_ERR_INVALID_ARG

@@ -38,11 +38,11 @@ def run_backward(g, vals, mlp, cams, g_rgba, ids=None, **kw):
             feat.grad.cpu().numpy(), out.detach().cpu().numpy())
 
 
-def compare(name, gpu, ref):
+def compare(name, gpu, ref, rel=1e-4):
     scale = float(np.abs(ref).max())
     err = float(np.abs(gpu - ref).max())
     say(f"  {name}: max|ref|={scale:.3e} max_err={err:.3e}")
-    assert err <= 1e-4 * scale + 1e-7, name
+    assert err <= rel * scale + 1e-7, name
 
 
 @pytest.mark.parametrize("n_occ,seed,early,mlp_on,subset", [(96, 4, False, True, False), (200, 2, True, True, False),
@@ -98,3 +98,36 @@ def test_mse_step_reduces_loss():
             m -= 0.5 * m.grad / (m.grad.norm() + 1e-12) * 0.05
     say(f"  losses {losses}")
     assert losses[-1] < losses[0]
+
+
+def test_fp16_mlp_backward_matches_oracle_gradient():
+    # Two bars.  Tight: against the same arithmetic with FP16 operands
+    # emulated in NumPy on the oracle's per-ray state (tests/fp16_reference.py),
+    # grid gradients from the FP64 oracle march fed the emulated dL/dC_d,
+    # dL/dV; the remaining differences are FP32 versus FP64 sums.  Loose:
+    # against the exact FP64 gradient; FP16 operand rounding (u = 2^-11) in a
+    # ReLU chain with cancelling sums measures about 2% of max|g| here.
+    from tests import fp16_reference as F
+    say("fp16 mlp backward vs FP16-emulated and exact oracle gradients")
+    seed = 2
+    g = W.tiny_grid(n_occupied=200, seed=seed)
+    vals = shadow_values(g, seed)
+    mlp = W.mlp_weights(seed + 1)
+    cams = [W.orbit_camera(48, 40, seed=seed + 2), W.orbit_camera(21, 35, seed=seed + 3)]
+    n = sum(c.n_rays for c in cams)
+    rng = np.random.default_rng(seed)
+    g_rgba = rng.normal(size=(n, 4)) / n
+    gm, gd, gr, gf, out = run_backward(g, vals, mlp, cams, g_rgba, fp16=True)
+    og = O.OracleGrid(g, values=vals)
+    aux = O.render(og, mlp, cams)["aux"]
+    dW16, gcv16 = F.mlp_backward_fp16(mlp, aux, F.directions(cams, g.N), g_rgba)
+    _, ed, er, ef = O.render_grad(og, mlp, cams, g_rgba, g_cv=gcv16)
+    compare("mlp vs fp16 emulation", gm, dW16, rel=1e-3)
+    compare("dens vs fp16 emulation", gd, ed, rel=1e-3)
+    compare("rgb vs fp16 emulation", gr, er, rel=1e-3)
+    compare("feat vs fp16 emulation", gf, ef, rel=1e-3)
+    om, od, orr, of = O.render_grad(og, mlp, cams, g_rgba)
+    for name, a_, b_ in (("mlp", gm, om), ("dens", gd, od), ("rgb", gr, orr), ("feat", gf, of)):
+        compare(name + " vs exact", a_, b_, rel=5e-2)
+    ref = O.render(og, mlp, cams)["rgba"]
+    assert np.abs(out - ref).max() <= 2e-3

@@ -128,3 +128,22 @@ def test_mlp_bias_gradient_for_zero_network():
     assert gate.any()
     assert np.allclose(gm[-3:], 0.25 * g_rgba[gate, :3].sum(axis=0), rtol=1e-13)
     assert np.all(gm[:-3] == 0.0)
+
+
+def test_gcv_override_matches_mlp_backward():
+    # Supplying each ray's dL/dC_d, dL/dV computed by an independent NumPy
+    # chain must reproduce the grid gradients of the oracle's own MLP backward.
+    from tests import fp16_reference as F
+    g = W.tiny_grid(n_occupied=96, seed=4)
+    og = O.OracleGrid(g, values=shadow_of(g))
+    mlp = W.mlp_weights(5)
+    cams = [W.orbit_camera(9, 8, seed=6)]
+    rng = np.random.default_rng(1)
+    g_rgba = rng.normal(size=(72, 4))
+    aux = O.render(og, mlp, cams)["aux"]
+    dW, gcv = F.mlp_backward_fp16(mlp, aux, F.directions(cams, g.N), g_rgba, round_operands=False)
+    gm, gd, gr, gf = O.render_grad(og, mlp, cams, g_rgba)
+    _, gd2, gr2, gf2 = O.render_grad(og, mlp, cams, g_rgba, g_cv=gcv)
+    assert np.allclose(dW, gm, rtol=1e-10, atol=1e-14)
+    for a_, b_ in ((gd, gd2), (gr, gr2), (gf, gf2)):
+        assert np.allclose(a_, b_, rtol=1e-10, atol=1e-14)
