@@ -155,6 +155,74 @@ def leg_adjoint(args, torch, S, W, O):
     return res
 
 
+def leg_large(args, torch, S, W, O):
+    """64 x 1920x1080 forward in one persistent graph launch (FP16 MLP), then
+    forward + backward on random 65,536-ray minibatches over all 64 views
+    (FP16 MLP forward and backward, float32 shadow of the grid)."""
+    from paper_2103_14645_amd import autograd as A
+    cfg = W.config("large1024")
+    g, cams, mlp = cfg["grid"], cfg["cams"], cfg["mlp"]
+    h = S.Handle()
+    dg = S.DeviceGrid(h, g.N, g.B, g.indirection, g.dens, g.rgb, g.feat)
+    m = S.mlp_tensor(mlp)
+    n = sum(c.n_rays for c in cams)
+    out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    carr = S.make_cameras(cams)
+    opts = S.make_opts(fp16=True, persistent=True, graph=True)
+    log(f"large1024: {g.n_blocks} blocks ({g.meta['occupancy']:.3f}), {len(cams)} cameras, {n} rays")
+    best, _ = S.snerg_autotune(h, dg.struct(), m, carr, opts, out, reps=1,
+                               candidates=[(8, 8, 4, 8), (8, 8, 2, 8), (8, 8, 4, 4), (16, 4, 4, 8)])
+    grid = dg.struct()
+
+    def step():
+        S.snerg_render(h, grid, m, carr, None, n, opts, out)
+
+    ms = time_launches(step, 2, 1, torch)
+    ids = torch.from_numpy(np.sort(np.random.default_rng(3).choice(n, 4096, replace=False))).cuda()
+    frame = out[ids].cpu().numpy()
+    ref = O.render(O.OracleGrid(g), mlp, cams, ray_ids=ids.cpu().numpy())["rgba"]
+    err = float(np.abs(frame - ref).max())
+    del out
+    # backward on minibatches of 65,536 rays
+    r = A.ShadowRenderer(h, g.N, g.B, g.indirection, g.n_blocks)
+    dens = torch.from_numpy(g.dens).cuda().float().div_(255.0)
+    rgb = torch.from_numpy(g.rgb).cuda().float().div_(255.0)
+    feat = torch.from_numpy(g.feat).cuda().float().div_(255.0)
+    r.pack(dens, rgb, feat)
+    sgrid = r.struct()
+    bopts = S.make_opts(fp16=True)
+    mb = 65536
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(3)
+    batches = [torch.randperm(n, device="cuda", generator=gen)[:mb].sort().values for _ in range(4)]
+    bout = torch.empty((mb, 4), device="cuda")
+    aux = torch.empty((mb, 8), device="cuda")
+    gout = torch.randn((mb, 4), device="cuda") / mb
+    gm = torch.empty(883, device="cuda")
+    gd, gr, gf = torch.empty_like(dens), torch.empty_like(rgb), torch.empty_like(feat)
+    it = [0]
+
+    def train_step():
+        b = batches[it[0] % len(batches)]
+        it[0] += 1
+        S.snerg_render(h, sgrid, m, carr, b, mb, bopts, bout, aux)
+        S.snerg_render_backward(h, sgrid, m, carr, b, mb, bopts, aux, gout, gm, gd, gr, gf)
+
+    def fwd_only():
+        b = batches[it[0] % len(batches)]
+        it[0] += 1
+        S.snerg_render(h, sgrid, m, carr, b, mb, bopts, bout, aux)
+
+    ms_step = time_launches(train_step, 8, 2, torch)
+    ms_f = time_launches(fwd_only, 8, 2, torch)
+    ms_b = max(ms_step - ms_f, 1e-6)
+    res = dict(ms=ms, rays=n, mrays=n / ms / 1e3, max_abs_err=err, tuning=list(best), mb=mb,
+               ms_train_step=ms_step, ms_mb_fwd=ms_f, bwd_mrays=mb / ms_b / 1e3)
+    log(f"large1024: {ms:.1f} ms/launch, {res['mrays']:.1f} Mrays/s, fp16 err {err:.2e}; minibatch fwd+bwd "
+        f"{ms_step:.2f} ms (bwd {res['bwd_mrays']:.1f} Mrays/s)")
+    return res
+
+
 def cpu_baseline(plain, O):
     """The FP64 oracle on the host cores, on every 4th ray of the 800x800 frame."""
     n = plain["rays"]
@@ -175,7 +243,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--legs", default="plain,batched,adjoint")
+    ap.add_argument("--legs", default="plain,batched,adjoint,large")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -196,6 +264,8 @@ def main():
         extra["batched_fp16_1024"] = leg_batched(args, torch, S, W, O)
     if "adjoint" in legs:
         extra["adjoint_512"] = leg_adjoint(args, torch, S, W, O)
+    if "large" in legs:
+        extra["large_1024"] = leg_large(args, torch, S, W, O)
 
     ms = plain["ms"]
     achieved = plain["alg_bytes"] / (ms * 1e-3) / 1e9
@@ -232,6 +302,14 @@ def main():
         legs_out["adjoint_512"] = {"bwd_mrays": round(a["bwd_mrays"], 3), "fwd_mrays": round(a["fwd_mrays"], 3),
                                    "ms_bwd": round(a["ms_bwd"], 4), "ms_fwd": round(a["ms_fwd"], 4),
                                    "rays": a["rays"]}
+    if "large_1024" in extra:
+        b = extra["large_1024"]
+        legs_out["large_1024"] = {"mrays": round(b["mrays"], 3), "ms": round(b["ms"], 3),
+                                  "fps_800x800_equiv": round(b["mrays"] / 0.64, 2),
+                                  "max_abs_err_vs_oracle": b["max_abs_err"], "rays": b["rays"],
+                                  "tuning": b["tuning"], "minibatch": b["mb"],
+                                  "ms_minibatch_fwd_bwd": round(b["ms_train_step"], 4),
+                                  "bwd_mrays": round(b["bwd_mrays"], 3)}
     line["legs"] = legs_out
     if not args.no_cpu_baseline:
         log("cpu baseline (FP64 oracle)")

@@ -126,15 +126,17 @@ typedef struct {
 /* Launch shape used by the forward kernels (chosen by snerg_autotune). */
 typedef struct {
     int32_t tile_w, tile_h;   /* pixels per wavefront tile, tile_w * tile_h == 64 */
-    int32_t waves_per_group;  /* wavefronts per workgroup: 1, 2, 4 or 8 */
+    int32_t waves_per_group;  /* wavefronts per workgroup: 1, 2 or 4 */
     int32_t groups_per_cu;    /* persistent launch: resident workgroups per compute unit, 1..16 */
 } snerg_tuning;
 
 /* ---------------------------------------------------------------- handles */
 
 /* Creates a handle on the current HIP device.  It owns small device buffers
- * (camera table, tile counter, reduction scratch), cached HIP graphs and
- * the tuning table; nothing the caller passes in. */
+ * (camera table, tile counter, the backward pass's MLP partial sums and
+ * per-ray dL/dC_d, dL/dV scratch, grown on demand), a cached HIP graph and
+ * the tuning; nothing the caller passes in.  Calls on one handle should use
+ * one stream (or the caller orders the streams). */
 int snerg_create(snerg_handle **out);
 int snerg_destroy(snerg_handle *h);
 

@@ -22,6 +22,17 @@ def directions(cams, N):
     return np.array([O.ray_setup(c, N, i, j)[2] for c in cams for j in range(c.H) for i in range(c.W)])
 
 
+def directions_of(cams, N, ray_ids):
+    """Directions of the given global ray ids (cameras in order, rows from the top)."""
+    offs = np.cumsum([0] + [c.W * c.H for c in cams])
+    out = []
+    for r in ray_ids:
+        ci = int(np.searchsorted(offs, r, side="right") - 1)
+        local = int(r - offs[ci])
+        out.append(O.ray_setup(cams[ci], N, local % cams[ci].W, local // cams[ci].W)[2])
+    return np.array(out)
+
+
 def mlp_backward_fp16(mlp, aux, dirs, g_rgba, round_operands=True):
     """aux: oracle aux rows [n, 9] (C_d, V, T, gate); dirs [n, 3]; g_rgba [n, 4]."""
     q = _h if round_operands else (lambda a: np.asarray(a, np.float64))

@@ -38,6 +38,15 @@ def run_backward(g, vals, mlp, cams, g_rgba, ids=None, **kw):
             feat.grad.cpu().numpy(), out.detach().cpu().numpy())
 
 
+def stable_ids(og, mlp, cams, ids):
+    """Drop rays whose early-stop decision lies within a relative 1e-5 of
+    t_stop (either branch would be a correct render, with another gradient)."""
+    alt = [O.render(og, mlp, cams, ray_ids=ids, t_stop=1e-3 * f)["counters"] for f in (1 - 1e-5, 1 + 1e-5)]
+    keep = np.all(alt[0] == alt[1], axis=1)
+    say(f"  dropped {int((~keep).sum())} near-threshold rays of {len(ids)}")
+    return ids[keep]
+
+
 def compare(name, gpu, ref, rel=1e-4):
     scale = float(np.abs(ref).max())
     err = float(np.abs(gpu - ref).max())
@@ -131,3 +140,49 @@ def test_fp16_mlp_backward_matches_oracle_gradient():
         compare(name + " vs exact", a_, b_, rel=5e-2)
     ref = O.render(og, mlp, cams)["rgba"]
     assert np.abs(out - ref).max() <= 2e-3
+
+
+def test_adjoint512_minibatch_full_size():
+    # The 512^3 adjoint grid at full size: a random minibatch of rays over 8
+    # 800x800 views, every grid value's gradient against the oracle's.
+    cfg = W.config("adjoint512")
+    g, cams, mlp = cfg["grid"], cfg["cams"], cfg["mlp"]
+    n = sum(c.n_rays for c in cams)
+    vals = (g.dens / np.float32(255.0), g.rgb / np.float32(255.0), g.feat / np.float32(255.0))
+    vals = tuple(np.ascontiguousarray(v, np.float32) for v in vals)
+    og = O.OracleGrid(g, values=vals)
+    ids = stable_ids(og, mlp, cams, np.sort(np.random.default_rng(3).choice(n, 4096, replace=False)))
+    rng = np.random.default_rng(5)
+    g_rgba = rng.normal(size=(len(ids), 4)) / len(ids)
+    say(f"adjoint512 minibatch: {len(ids)} rays of {n}, {g.n_blocks} blocks")
+    gm, gd, gr, gf, _ = run_backward(g, vals, mlp, cams, g_rgba, ids=ids)
+    om, od, orr, of = O.render_grad(og, mlp, cams, g_rgba, ray_ids=ids)
+    compare("mlp", gm, om)
+    compare("dens", gd, od)
+    compare("rgb", gr, orr)
+    compare("feat", gf, of)
+
+
+def test_large1024_fp16_minibatch_full_size():
+    # The 1024^3 (8% occupied) grid with the FP16 MLP forward and backward on a
+    # random minibatch over the 64 1080p views, against the FP16 emulation
+    # (tight) and the exact gradient (loose), as in the 64^3 FP16 test.
+    from tests import fp16_reference as F
+    cfg = W.config("large1024")
+    g, cams, mlp = cfg["grid"], cfg["cams"], cfg["mlp"]
+    n = sum(c.n_rays for c in cams)
+    vals = tuple(np.ascontiguousarray(v / np.float32(255.0), np.float32) for v in (g.dens, g.rgb, g.feat))
+    og = O.OracleGrid(g, values=vals)
+    ids = stable_ids(og, mlp, cams, np.sort(np.random.default_rng(3).choice(n, 2048, replace=False)))
+    rng = np.random.default_rng(6)
+    g_rgba = rng.normal(size=(len(ids), 4)) / len(ids)
+    say(f"large1024 fp16 minibatch: {len(ids)} rays of {n}, {g.n_blocks} blocks")
+    gm, gd, gr, gf, _ = run_backward(g, vals, mlp, cams, g_rgba, ids=ids, fp16=True)
+    aux = O.render(og, mlp, cams, ray_ids=ids)["aux"]
+    dirs = F.directions_of(cams, g.N, ids)
+    dW16, gcv16 = F.mlp_backward_fp16(mlp, aux, dirs, g_rgba)
+    _, ed, er, ef = O.render_grad(og, mlp, cams, g_rgba, ray_ids=ids, g_cv=gcv16)
+    compare("mlp vs fp16 emulation", gm, dW16, rel=1e-3)
+    compare("dens vs fp16 emulation", gd, ed, rel=1e-3)
+    compare("rgb vs fp16 emulation", gr, er, rel=1e-3)
+    compare("feat vs fp16 emulation", gf, ef, rel=1e-3)

@@ -176,3 +176,22 @@ def test_zero_rays_is_a_no_op():
                    torch.zeros(1, dtype=torch.int64, device="cuda"), 0, S.make_opts(), out)
     torch.cuda.synchronize()
     assert torch.all(out == 7.0)
+
+
+def test_large1024_all_cameras_one_launch_sampled():
+    # 64 cameras at 1920x1080 in one persistent graph launch with the FP16 MLP,
+    # the configuration the benchmark times; 4,000 sampled rays vs the oracle.
+    cfg = W.config("large1024")
+    g, cams, mlp = cfg["grid"], cfg["cams"], cfg["mlp"]
+    n = sum(c.n_rays for c in cams)
+    say(f"large1024: {len(cams)} cameras, {n} rays, {g.n_blocks} blocks")
+    dg = device_grid(g)
+    out = S.render(handle(), dg, S.mlp_tensor(mlp), cams,
+                   opts=S.make_opts(fp16=True, persistent=True, graph=True))
+    ids = np.sort(np.random.default_rng(11).choice(n, 4000, replace=False))
+    got = out[torch.from_numpy(ids).cuda()].cpu().numpy()
+    del out
+    og = O.OracleGrid(g)
+    err, flagged = parity_error(got, oracle_variants(og, mlp, cams, ids=ids))
+    say(f"  fp16 max_err={err.max():.3e} near_threshold={flagged} hit_frac={(got[:, 3] > 0).mean():.3f}")
+    assert err.max() <= TOL_F16
