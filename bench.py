@@ -1,6 +1,8 @@
 """Throughput of the SNeRG render path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs plain,batched,adjoint]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs plain,batched,adjoint,large]
+    python bench.py --legs plain,copy --no-cpu-baseline   # adds the copy-kernel calibration launches
+    python bench.py --source-hash                          # hash of the render kernel sources
 
 Headline (value): forward Mrays/s of the plain FP32 path on the 512^3 grid
 (B = 32, ~10.6% occupied procedural shell) for one 800x800 camera, with
@@ -10,10 +12,16 @@ cameras of mixed size in one persistent launch replayed from a HIP graph)
 with its max-abs error against the FP64 oracle, and the adjoint (8 views at
 800x800 on a float32 shadow of the 512^3 grid, forward + backward).
 Prints one JSON line on stdout; progress goes to stderr.
+
+roofline.traffic is the measured HBM traffic of one render launch, read from
+the committed counter summary for this kernel and workload; it is reported
+only while the hash of the render kernel sources equals the one recorded
+there (the counters describe that code), else null.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,6 +34,33 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+RENDER_SOURCES = ("render.hip", "march.h", "mlp.h", "snerg_dev.h", "snerg_launch.h")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_render_plain512_traffic.md")
+COPY_BYTES = 1 << 30
+
+
+def render_source_hash():
+    h = hashlib.sha256()
+    for name in RENDER_SOURCES:
+        with open(os.path.join(ROOT, "paper_2103_14645_amd", "csrc", name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """Bytes per launch from the committed counter summary, if it describes
+    the current kernel sources ("key = value" lines), else None."""
+    try:
+        kv = {}
+        for line in open(TRAFFIC_SUMMARY):
+            if "=" in line and not line.startswith(" "):
+                k, v = line.split("=", 1)
+                kv[k.strip().strip("`")] = v.strip().strip("`")
+        if kv.get("render_source_sha256") != render_source_hash():
+            return None
+        return int(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def log(msg):
@@ -223,10 +258,25 @@ def leg_large(args, torch, S, W, O):
     return res
 
 
+def leg_copy(torch):
+    """A plain 1 GiB device-to-device copy (torch's elementwise copy kernel),
+    launched three times: what FETCH_SIZE and WRITE_SIZE read for it against
+    the 1 GiB it moves each way calibrates those counters."""
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ms = time_launches(lambda: dst.copy_(src), 5, 1, torch)
+    log(f"copy: {COPY_BYTES} B each way, {ms:.3f} ms, {2 * COPY_BYTES / ms / 1e6:.1f} GB/s")
+    del src, dst
+    return dict(ms=ms, bytes=COPY_BYTES, gbs=2 * COPY_BYTES / ms / 1e6)
+
+
 def cpu_baseline(plain, O):
-    """The FP64 oracle on the host cores, on every 4th ray of the 800x800 frame."""
+    """The FP64 oracle on the host cores over the whole 800x800 frame."""
     n = plain["rays"]
-    ids = np.arange(0, n, 4, dtype=np.int64)
+    ids = np.arange(0, n, dtype=np.int64)
     og = O.OracleGrid(plain["g"])
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
@@ -234,7 +284,7 @@ def cpu_baseline(plain, O):
     dt = time.perf_counter() - t0
     err = float(np.abs(plain["out"].cpu().numpy()[ids] - ref).max())
     return dict(value=len(ids) / dt / 1e6, unit="Mrays/s", cores=threads, kind="oracle",
-                sample=f"every 4th ray of the 800x800 frame ({len(ids)} rays), {dt:.1f} s",
+                sample=f"all {len(ids)} rays of the 800x800 frame, {dt:.1f} s wall on {threads} threads",
                 gpu_max_abs_err=err)
 
 
@@ -245,7 +295,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--legs", default="plain,batched,adjoint,large")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--source-hash", action="store_true")
     args = ap.parse_args()
+    if args.source_hash:
+        print(render_source_hash())
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the render shards by rays "
               f"with no communication; see the design notes)", file=sys.stderr)
@@ -266,6 +320,8 @@ def main():
         extra["adjoint_512"] = leg_adjoint(args, torch, S, W, O)
     if "large" in legs:
         extra["large_1024"] = leg_large(args, torch, S, W, O)
+    if "copy" in legs:
+        extra["copy"] = leg_copy(torch)
 
     ms = plain["ms"]
     achieved = plain["alg_bytes"] / (ms * 1e-3) / 1e9
@@ -286,7 +342,7 @@ def main():
                                "one 800x800 camera (39 deg), FP32 34-16-16-3 MLP",
                    "fps_800x800": round(1000.0 / ms, 2), "rays": plain["rays"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "kernel": "k_render<u8, fp32-mlp>", "alg_bytes_per_launch": plain["alg_bytes"],
                      "counters": plain["counters"]},
     }
@@ -310,6 +366,8 @@ def main():
                                   "tuning": b["tuning"], "minibatch": b["mb"],
                                   "ms_minibatch_fwd_bwd": round(b["ms_train_step"], 4),
                                   "bwd_mrays": round(b["bwd_mrays"], 3)}
+    if "copy" in extra:
+        legs_out["copy_calibration"] = {k: round(v, 4) for k, v in extra["copy"].items()}
     line["legs"] = legs_out
     if not args.no_cpu_baseline:
         log("cpu baseline (FP64 oracle)")
