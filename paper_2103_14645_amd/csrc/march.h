@@ -16,8 +16,14 @@ struct Sample {
     bool active;
 };
 
-__device__ __forceinline__ uint2 ld_u2(const uint8_t* p) {
-    return *reinterpret_cast<const uint2*>(p);
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// 16 bytes at an 8-byte aligned address: one dwordx4 load (global memory
+// needs only dword alignment for multi-dword accesses).
+__device__ __forceinline__ u32x4 ld_pair(const uint8_t* p) {
+    u32x4 v;
+    __builtin_memcpy(&v, __builtin_assume_aligned(p, 8), 16);
+    return v;
 }
 
 __device__ __forceinline__ float ubyte(uint32_t v, int i) {
@@ -45,20 +51,24 @@ __device__ __forceinline__ bool corner_live(int c, const int32_t fr[3]) {
     return ((c & 1) == 0 || fr[0] != 0) && ((c & 2) == 0 || fr[1] != 0) && ((c & 4) == 0 || fr[2] != 0);
 }
 
-// Gather at padded cell p (each in [0, B]) of a uint8 block.
+// Gather at padded cell p (each in [0, B]) of a uint8 block.  The corners
+// (x, x+1) of each of the four (y, z) rows are 16 adjacent bytes, so the
+// 8 corners arrive in four 16-byte loads issued together.
 __device__ __forceinline__ void gather_u8(const uint8_t* __restrict__ blk, int Bp, const int32_t p[3],
                                           const int32_t fr[3], Sample& smp) {
     const uint8_t* base = blk + (int64_t((p[2] * Bp + p[1]) * Bp + p[0]) << 3);
     const int sy = Bp * 8, sz = Bp * Bp * 8;
+    const u32x4 q0 = ld_pair(base), q1 = ld_pair(base + sy);
+    const u32x4 q2 = ld_pair(base + sz), q3 = ld_pair(base + sz + sy);
     uint2 v[8];
-    v[0] = ld_u2(base);
-    v[1] = ld_u2(base + 8);
-    v[2] = ld_u2(base + sy);
-    v[3] = ld_u2(base + sy + 8);
-    v[4] = ld_u2(base + sz);
-    v[5] = ld_u2(base + sz + 8);
-    v[6] = ld_u2(base + sz + sy);
-    v[7] = ld_u2(base + sz + sy + 8);
+    v[0] = make_uint2(q0.x, q0.y);
+    v[1] = make_uint2(q0.z, q0.w);
+    v[2] = make_uint2(q1.x, q1.y);
+    v[3] = make_uint2(q1.z, q1.w);
+    v[4] = make_uint2(q2.x, q2.y);
+    v[5] = make_uint2(q2.z, q2.w);
+    v[6] = make_uint2(q3.x, q3.y);
+    v[7] = make_uint2(q3.z, q3.w);
     float w[8];
     corner_weights(fr, w);
     float sd = 0.f, r0 = 0.f, r1 = 0.f, r2 = 0.f, f0 = 0.f, f1 = 0.f, f2 = 0.f, f3 = 0.f;

@@ -48,6 +48,15 @@ __device__ __forceinline__ void march_composite(const RenderArgs& a, const uint2
         });
 }
 
+// The wavefront's tile or first ray index is the same in every lane; saying
+// so keeps the camera lookup and everything derived from it in scalar
+// registers.
+__device__ __forceinline__ int64_t wave_uniform(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v)));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v) >> 32));
+    return int64_t((uint64_t(hi) << 32) | lo);
+}
+
 // Copies the occupancy table into LDS (all threads of the workgroup call this).
 __device__ __forceinline__ const uint2* stage_occupancy(const GridArgs& g) {
     extern __shared__ uint2 s_occ[];
@@ -121,6 +130,7 @@ __global__ __launch_bounds__(256) void k_render(RenderArgs a) {
             if (lane == 0) v = atomicAdd(a.tile_counter, 1);
             t = __shfl(v, 0);
         }
+        t = wave_uniform(t);
         bool valid;
         int ci = 0, px = 0, py = 0;
         int64_t out_idx;
