@@ -476,6 +476,9 @@ int snerg_render_backward(snerg_handle* h, const snerg_grid* grid, const float* 
     a.grad_dens = grad_dens;
     a.grad_rgb = grad_rgb;
     a.grad_feat = grad_feat;
+    a.total_tiles = total_tiles;
+    a.tile_w = h->tuning.tile_w;
+    a.tile_h = h->tuning.tile_h;
     HIP_TRY(launch_backward(a, n_groups, s));
     if (mlp_mode != kMlpOff) HIP_TRY(launch_reduce_mlp(h->d_partial, rows, grad_mlp, s));
     return SNERG_OK;

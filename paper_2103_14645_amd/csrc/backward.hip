@@ -361,60 +361,183 @@ struct CellWindow {
     float A[8], D[8];
 };
 
-template <bool FEAT>
-__device__ __forceinline__ void flush_corner(const BackwardArgs& a, const CellWindow& w, int c, const float gC[3],
-                                             const float gV[4]) {
+// Per-wavefront gradient aggregation in LDS.  The rays of an 8x8 pixel tile
+// share most of the voxels they touch, so each voxel's eight gradient values
+// (density, RGB, features) are first summed in an open-addressed table of
+// kAggSlots entries and reach device memory with one set of atomics per
+// table flush instead of one per ray.  Keys are canonical voxel indices
+// (< 2^31; the launch falls back to direct atomics otherwise).
+constexpr int kAggSlots = 512;
+constexpr int kAggLog = 9;
+constexpr int kAggProbes = 8;
+constexpr int kAggFlushAt = kAggSlots / 2;  // flush once this many keys are in
+constexpr int kAggWaves = 4;                 // wavefronts per workgroup
+constexpr int kAggWords = kAggSlots * 9 + 1; // keys, 8 value planes, key count
+
+struct AggTable {
+    int32_t* key;  // [kAggSlots], -1 = free
+    float* val;    // [8][kAggSlots]
+    int32_t* n;    // keys inserted since the last flush
+};
+
+__device__ __forceinline__ void add_global(const BackwardArgs& a, int64_t vi, const float v[8], bool feat) {
+    unsafeAtomicAdd(a.grad_dens + vi, v[0]);
+    unsafeAtomicAdd(a.grad_rgb + 3 * vi + 0, v[1]);
+    unsafeAtomicAdd(a.grad_rgb + 3 * vi + 1, v[2]);
+    unsafeAtomicAdd(a.grad_rgb + 3 * vi + 2, v[3]);
+    if (feat) {
+        unsafeAtomicAdd(a.grad_feat + 4 * vi + 0, v[4]);
+        unsafeAtomicAdd(a.grad_feat + 4 * vi + 1, v[5]);
+        unsafeAtomicAdd(a.grad_feat + 4 * vi + 2, v[6]);
+        unsafeAtomicAdd(a.grad_feat + 4 * vi + 3, v[7]);
+    }
+}
+
+// Adds v to the table entry of `key` (lanes may diverge); false when no slot
+// was found within kAggProbes probes.
+__device__ __forceinline__ bool agg_add(const AggTable& t, int32_t key, const float v[8], bool feat) {
+    const uint32_t h = (uint32_t(key) * 2654435761u) >> (32 - kAggLog);
+    for (int pr = 0; pr < kAggProbes; ++pr) {
+        const uint32_t sl = (h + pr) & (kAggSlots - 1);
+        int32_t k = __hip_atomic_load(t.key + sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        if (k == -1) {
+            k = atomicCAS(t.key + sl, -1, key);
+            if (k == -1) {
+                atomicAdd(t.n, 1);
+                k = key;
+            }
+        }
+        if (k == key) {
+            const int nv = feat ? 8 : 4;
+            for (int c = 0; c < nv; ++c) atomicAdd(t.val + c * kAggSlots + sl, v[c]);
+            return true;
+        }
+    }
+    return false;
+}
+
+// All 64 lanes together: every used entry goes to device memory, the table
+// is cleared.
+__device__ __forceinline__ void agg_flush(const BackwardArgs& a, const AggTable& t, int lane, bool feat) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int sl = lane; sl < kAggSlots; sl += 64) {
+        const int32_t key = t.key[sl];
+        if (key >= 0) {
+            float v[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                v[c] = t.val[c * kAggSlots + sl];
+                t.val[c * kAggSlots + sl] = 0.0f;
+            }
+            add_global(a, key, v, feat);
+            t.key[sl] = -1;
+        }
+    }
+    if (lane == 0) *t.n = 0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <bool FEAT, bool AGG>
+__device__ __forceinline__ void flush_corner(const BackwardArgs& a, const AggTable& t, const CellWindow& w, int c,
+                                             const float gC[3], const float gV[4]) {
     const float A = w.A[c], D = w.D[c];
     if (A == 0.0f && D == 0.0f) return;
     const GridArgs& g = a.grid;
     const int64_t vi = canonical_voxel(g, w.id, w.b, w.c[0] + (c & 1) - 1, w.c[1] + ((c >> 1) & 1) - 1,
                                        w.c[2] + (c >> 2) - 1);
     if (vi < 0) return;
-    unsafeAtomicAdd(a.grad_dens + vi, g.sigma_scale * D);
-    unsafeAtomicAdd(a.grad_rgb + 3 * vi + 0, A * gC[0]);
-    unsafeAtomicAdd(a.grad_rgb + 3 * vi + 1, A * gC[1]);
-    unsafeAtomicAdd(a.grad_rgb + 3 * vi + 2, A * gC[2]);
+    float v[8] = {g.sigma_scale * D, A * gC[0], A * gC[1], A * gC[2], 0.f, 0.f, 0.f, 0.f};
     if (FEAT) {
-        unsafeAtomicAdd(a.grad_feat + 4 * vi + 0, A * gV[0]);
-        unsafeAtomicAdd(a.grad_feat + 4 * vi + 1, A * gV[1]);
-        unsafeAtomicAdd(a.grad_feat + 4 * vi + 2, A * gV[2]);
-        unsafeAtomicAdd(a.grad_feat + 4 * vi + 3, A * gV[3]);
+        v[4] = A * gV[0]; v[5] = A * gV[1]; v[6] = A * gV[2]; v[7] = A * gV[3];
     }
+    if (AGG && agg_add(t, int32_t(vi), v, FEAT)) return;
+    add_global(a, vi, v, FEAT);
 }
 
-template <bool FEAT>
-__global__ __launch_bounds__(256) void k_march_backward(BackwardArgs a) {
+// One lane per ray.  Without a ray list the wavefronts walk the cameras'
+// tt_w x tt_h pixel tiles (neighbouring rays, shared voxels); with a list,
+// 64 consecutive list entries.  AGG: gradients go through the per-wavefront
+// LDS table.  Every lane stays to the end (the flushes need all 64).
+template <bool FEAT, bool AGG>
+__global__ __launch_bounds__(64 * kAggWaves) void k_march_backward(BackwardArgs a) {
     extern __shared__ uint2 s_occ[];
-    for (int w = threadIdx.x; w < a.grid.n_words; w += blockDim.x) s_occ[w] = a.grid.occ[w];
-    __syncthreads();
     const GridArgs& g = a.grid;
+    for (int w = threadIdx.x; w < g.n_words; w += blockDim.x) s_occ[w] = g.occ[w];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    AggTable tab;
+    {
+        int32_t* base = reinterpret_cast<int32_t*>(s_occ + g.n_words) + wave * kAggWords;
+        tab.key = base;
+        tab.val = reinterpret_cast<float*>(base + kAggSlots);
+        tab.n = base + 9 * kAggSlots;
+        if (AGG) {
+            for (int sl = lane; sl < kAggSlots; sl += 64) {
+                tab.key[sl] = -1;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) tab.val[c * kAggSlots + sl] = 0.0f;
+            }
+            if (lane == 0) *tab.n = 0;
+        }
+    }
+    __syncthreads();
     const float delta = 1.0f / float(g.N);
     const float kx = g.sigma_scale * delta;
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= a.n_rays) return;
-    const float4 a1 = reinterpret_cast<const float4*>(a.aux)[2 * i + 1];
-    if (!(a1.w >= 0.0f)) return;  // nothing was composited: no grid gradient
-    const float4 a0 = reinterpret_cast<const float4*>(a.aux)[2 * i];
-    const float4 gg = reinterpret_cast<const float4*>(a.grad_rgba)[i];
-    float gC[3] = {gg.x, gg.y, gg.z}, gV[4] = {0.f, 0.f, 0.f, 0.f};
-    if (FEAT) {
-        const float4 c0 = reinterpret_cast<const float4*>(a.gcv)[2 * i];
-        const float4 c1 = reinterpret_cast<const float4*>(a.gcv)[2 * i + 1];
-        gC[0] = c0.x; gC[1] = c0.y; gC[2] = c0.z;
-        gV[0] = c0.w; gV[1] = c1.x; gV[2] = c1.y; gV[3] = c1.z;
+
+    // this lane's ray: list position i (indexes aux, grad_rgba, gcv) and id r
+    bool live;
+    int64_t i, r;
+    const int64_t wt = int64_t(blockIdx.x) * kAggWaves + wave;
+    if (a.ray_ids) {
+        i = wt * 64 + lane;
+        live = i < a.n_rays;
+        r = live ? a.ray_ids[i] : 0;
+    } else {
+        live = wt < a.total_tiles;
+        i = r = 0;
+        if (live) {
+            const int ci = find_camera_by_tile(a.cams, a.n_cams, wt);
+            const DevCamera& c = a.cams[ci];
+            const int64_t tl = wt - c.tile_offset;
+            const int px = int(tl % c.tiles_x) * a.tile_w + lane % a.tile_w;
+            const int py = int(tl / c.tiles_x) * a.tile_h + lane / a.tile_w;
+            live = px < c.W && py < c.H;
+            i = r = c.ray_offset + int64_t(py) * c.W + px;
+        }
+    }
+    float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = make_float4(0.f, 0.f, 0.f, -1.f);
+    float4 gg = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (live) {
+        a1 = reinterpret_cast<const float4*>(a.aux)[2 * i + 1];
+        live = a1.w >= 0.0f;  // nothing was composited: no grid gradient
+    }
+    float gC[3] = {0.f, 0.f, 0.f}, gV[4] = {0.f, 0.f, 0.f, 0.f};
+    if (live) {
+        a0 = reinterpret_cast<const float4*>(a.aux)[2 * i];
+        gg = reinterpret_cast<const float4*>(a.grad_rgba)[i];
+        gC[0] = gg.x; gC[1] = gg.y; gC[2] = gg.z;
+        if (FEAT) {
+            const float4 c0 = reinterpret_cast<const float4*>(a.gcv)[2 * i];
+            const float4 c1 = reinterpret_cast<const float4*>(a.gcv)[2 * i + 1];
+            gC[0] = c0.x; gC[1] = c0.y; gC[2] = c0.z;
+            gV[0] = c0.w; gV[1] = c1.x; gV[2] = c1.y; gV[3] = c1.z;
+        }
     }
     const float E = gC[0] * a0.x + gC[1] * a0.y + gC[2] * a0.z +
                     (gV[0] * a0.w + gV[1] * a1.x + gV[2] * a1.y + gV[3] * a1.z);
     const float gTN = gg.x * a.opts.bg[0] + gg.y * a.opts.bg[1] + gg.z * a.opts.bg[2] - gg.w;
     const float tail = a1.w * gTN;
 
-    const int64_t r = a.ray_ids ? a.ray_ids[i] : i;
-    int ci, px, py;
-    locate(a, r, ci, px, py);
-    int64_t o[3];
-    int32_t s[3];
-    float d[3];
-    ray_setup(a.cams[ci], g.N, px, py, o, s, d);
+    int64_t o[3] = {0, 0, 0};
+    int32_t s[3] = {0, 0, 1 << 15};
+    if (live) {
+        int ci, px, py;
+        locate(a, r, ci, px, py);
+        float d[3];
+        ray_setup(a.cams[ci], g.N, px, py, o, s, d);
+    }
 
     CellWindow win;
     win.rank = -1;
@@ -426,8 +549,8 @@ __global__ __launch_bounds__(256) void k_march_backward(BackwardArgs a) {
     float T = 1.0f, Pk = 0.0f;
     const float t_stop = a.opts.t_stop;
     const bool early = a.opts.early_stop != 0;
-    march_ray(
-        g, s_occ, o, s, [](int32_t, bool) {}, [](int32_t) {},
+    march_ray_sync(
+        g, s_occ, live, o, s,
         [&](int64_t, int32_t rk, const uint8_t* vox, const int32_t p[3], const int32_t fr[3]) {
             Sample smp;
             gather_f32(vox, g.Bp, p, fr, smp);
@@ -460,7 +583,7 @@ __global__ __launch_bounds__(256) void k_march_backward(BackwardArgs a) {
             }
 #pragma unroll
             for (int c = 0; c < 8; ++c)
-                if ((leave >> c) & 1u) flush_corner<FEAT>(a, win, c, gC, gV);
+                if ((leave >> c) & 1u) flush_corner<FEAT, AGG>(a, tab, win, c, gC, gV);
             if (jump) {
 #pragma unroll
                 for (int c = 0; c < 8; ++c) win.A[c] = win.D[c] = 0.0f;
@@ -496,11 +619,16 @@ __global__ __launch_bounds__(256) void k_march_backward(BackwardArgs a) {
                 win.D[c] = fmaf(wc[c], gsig, win.D[c]);
             }
             return early && T < t_stop;
+        },
+        [&]() {
+            if (AGG && __hip_atomic_load(tab.n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) >= kAggFlushAt)
+                agg_flush(a, tab, lane, FEAT);
         });
     if (win.rank >= 0) {
 #pragma unroll
-        for (int c = 0; c < 8; ++c) flush_corner<FEAT>(a, win, c, gC, gV);
+        for (int c = 0; c < 8; ++c) flush_corner<FEAT, AGG>(a, tab, win, c, gC, gV);
     }
+    if (AGG) agg_flush(a, tab, lane, FEAT);
 }
 
 __global__ void k_reduce_rows(const float* __restrict__ partial, int rows, float* __restrict__ out) {
@@ -523,12 +651,21 @@ hipError_t launch_backward(const BackwardArgs& a, int n_groups, hipStream_t s) {
         hipLaunchKernelGGL(k_mlp_backward<false>, dim3(n_groups), dim3(64 * kBwdWaves), 0, s, a);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    const size_t lds = size_t(a.grid.n_words) * sizeof(uint2);
-    const unsigned blocks = unsigned((a.n_rays + 255) / 256);
-    if (a.mlp_mode != kMlpOff)
-        hipLaunchKernelGGL(k_march_backward<true>, dim3(blocks), dim3(256), lds, s, a);
+    // aggregation keys are int32 voxel indices
+    const int64_t n_vox = int64_t(a.grid.n_blocks) * a.grid.B * a.grid.B * a.grid.B;
+    const bool agg = !a.ray_ids && n_vox < (int64_t(1) << 31);
+    const size_t lds = size_t(a.grid.n_words) * sizeof(uint2) + (agg ? size_t(kAggWaves) * kAggWords * 4 : 0);
+    const int64_t waves = a.ray_ids ? (a.n_rays + 63) / 64 : a.total_tiles;
+    const unsigned blocks = unsigned((waves + kAggWaves - 1) / kAggWaves);
+    const bool feat = a.mlp_mode != kMlpOff;
+    if (feat && agg)
+        hipLaunchKernelGGL((k_march_backward<true, true>), dim3(blocks), dim3(64 * kAggWaves), lds, s, a);
+    else if (feat)
+        hipLaunchKernelGGL((k_march_backward<true, false>), dim3(blocks), dim3(64 * kAggWaves), lds, s, a);
+    else if (agg)
+        hipLaunchKernelGGL((k_march_backward<false, true>), dim3(blocks), dim3(64 * kAggWaves), lds, s, a);
     else
-        hipLaunchKernelGGL(k_march_backward<false>, dim3(blocks), dim3(256), lds, s, a);
+        hipLaunchKernelGGL((k_march_backward<false, false>), dim3(blocks), dim3(64 * kAggWaves), lds, s, a);
     return hipGetLastError();
 }
 

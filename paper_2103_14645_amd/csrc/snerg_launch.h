@@ -54,6 +54,8 @@ struct BackwardArgs {
     float* grad_dens;
     float* grad_rgb;
     float* grad_feat;
+    int64_t total_tiles;   // tile_w x tile_h tiles over all cameras (no ray list)
+    int32_t tile_w, tile_h;
 };
 
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
