@@ -372,12 +372,11 @@ constexpr int kAggLog = 9;
 constexpr int kAggProbes = 8;
 constexpr int kAggFlushAt = kAggSlots / 2;  // flush once this many keys are in
 constexpr int kAggWaves = 4;                 // wavefronts per workgroup
-constexpr int kAggWords = kAggSlots * 9 + 1; // keys, 8 value planes, key count
+constexpr int kAggWords = kAggSlots * 9;     // keys, 8 value planes
 
 struct AggTable {
     int32_t* key;  // [kAggSlots], -1 = free
     float* val;    // [8][kAggSlots]
-    int32_t* n;    // keys inserted since the last flush
 };
 
 __device__ __forceinline__ void add_global(const BackwardArgs& a, int64_t vi, const float v[8], bool feat) {
@@ -394,8 +393,8 @@ __device__ __forceinline__ void add_global(const BackwardArgs& a, int64_t vi, co
 }
 
 // Adds v to the table entry of `key` (lanes may diverge); false when no slot
-// was found within kAggProbes probes.
-__device__ __forceinline__ bool agg_add(const AggTable& t, int32_t key, const float v[8], bool feat) {
+// was found within kAggProbes probes.  `fresh` counts the lane's new keys.
+__device__ __forceinline__ bool agg_add(const AggTable& t, int32_t key, const float v[8], bool feat, int& fresh) {
     const uint32_t h = (uint32_t(key) * 2654435761u) >> (32 - kAggLog);
     for (int pr = 0; pr < kAggProbes; ++pr) {
         const uint32_t sl = (h + pr) & (kAggSlots - 1);
@@ -403,7 +402,7 @@ __device__ __forceinline__ bool agg_add(const AggTable& t, int32_t key, const fl
         if (k == -1) {
             k = atomicCAS(t.key + sl, -1, key);
             if (k == -1) {
-                atomicAdd(t.n, 1);
+                ++fresh;
                 k = key;
             }
         }
@@ -434,14 +433,19 @@ __device__ __forceinline__ void agg_flush(const BackwardArgs& a, const AggTable&
             t.key[sl] = -1;
         }
     }
-    if (lane == 0) *t.n = 0;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
 
+__device__ __forceinline__ int wave_sum_i32(int v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
 template <bool FEAT, bool AGG>
 __device__ __forceinline__ void flush_corner(const BackwardArgs& a, const AggTable& t, const CellWindow& w, int c,
-                                             const float gC[3], const float gV[4]) {
+                                             const float gC[3], const float gV[4], int& fresh) {
     const float A = w.A[c], D = w.D[c];
     if (A == 0.0f && D == 0.0f) return;
     const GridArgs& g = a.grid;
@@ -452,7 +456,7 @@ __device__ __forceinline__ void flush_corner(const BackwardArgs& a, const AggTab
     if (FEAT) {
         v[4] = A * gV[0]; v[5] = A * gV[1]; v[6] = A * gV[2]; v[7] = A * gV[3];
     }
-    if (AGG && agg_add(t, int32_t(vi), v, FEAT)) return;
+    if (AGG && agg_add(t, int32_t(vi), v, FEAT, fresh)) return;
     add_global(a, vi, v, FEAT);
 }
 
@@ -472,14 +476,12 @@ __global__ __launch_bounds__(64 * kAggWaves) void k_march_backward(BackwardArgs 
         int32_t* base = reinterpret_cast<int32_t*>(s_occ + g.n_words) + wave * kAggWords;
         tab.key = base;
         tab.val = reinterpret_cast<float*>(base + kAggSlots);
-        tab.n = base + 9 * kAggSlots;
         if (AGG) {
             for (int sl = lane; sl < kAggSlots; sl += 64) {
                 tab.key[sl] = -1;
 #pragma unroll
                 for (int c = 0; c < 8; ++c) tab.val[c * kAggSlots + sl] = 0.0f;
             }
-            if (lane == 0) *tab.n = 0;
         }
     }
     __syncthreads();
@@ -547,6 +549,8 @@ __global__ __launch_bounds__(64 * kAggWaves) void k_march_backward(BackwardArgs 
 #pragma unroll
     for (int c = 0; c < 8; ++c) win.A[c] = win.D[c] = 0.0f;
     float T = 1.0f, Pk = 0.0f;
+    int fresh = 0;    // this lane's new table keys since the last count
+    int in_table = 0; // wave-uniform: keys in the table
     const float t_stop = a.opts.t_stop;
     const bool early = a.opts.early_stop != 0;
     march_ray_sync(
@@ -583,7 +587,7 @@ __global__ __launch_bounds__(64 * kAggWaves) void k_march_backward(BackwardArgs 
             }
 #pragma unroll
             for (int c = 0; c < 8; ++c)
-                if ((leave >> c) & 1u) flush_corner<FEAT, AGG>(a, tab, win, c, gC, gV);
+                if ((leave >> c) & 1u) flush_corner<FEAT, AGG>(a, tab, win, c, gC, gV, fresh);
             if (jump) {
 #pragma unroll
                 for (int c = 0; c < 8; ++c) win.A[c] = win.D[c] = 0.0f;
@@ -621,22 +625,40 @@ __global__ __launch_bounds__(64 * kAggWaves) void k_march_backward(BackwardArgs 
             return early && T < t_stop;
         },
         [&]() {
-            if (AGG && __hip_atomic_load(tab.n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) >= kAggFlushAt)
-                agg_flush(a, tab, lane, FEAT);
+            if (AGG && __any(fresh != 0)) {
+                in_table += wave_sum_i32(fresh);
+                fresh = 0;
+                if (in_table >= kAggFlushAt) {
+                    agg_flush(a, tab, lane, FEAT);
+                    in_table = 0;
+                }
+            }
         });
     if (win.rank >= 0) {
 #pragma unroll
-        for (int c = 0; c < 8; ++c) flush_corner<FEAT, AGG>(a, tab, win, c, gC, gV);
+        for (int c = 0; c < 8; ++c) flush_corner<FEAT, AGG>(a, tab, win, c, gC, gV, fresh);
     }
     if (AGG) agg_flush(a, tab, lane, FEAT);
 }
 
-__global__ void k_reduce_rows(const float* __restrict__ partial, int rows, float* __restrict__ out) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= kMlpParams) return;
-    float s = 0.f;
-    for (int r = 0; r < rows; ++r) s += partial[int64_t(r) * kMlpParams + j];
-    out[j] = s;
+// Column sums of the [rows][883] partial-gradient matrix into out (which
+// holds zeros): each workgroup takes 64 columns x kReduceRows rows, four
+// row phases of 64 threads, combines them in LDS and adds its sum to out.
+constexpr int kReduceRows = 256;
+
+__global__ __launch_bounds__(256) void k_reduce_rows(const float* __restrict__ partial, int rows,
+                                                     float* __restrict__ out) {
+    __shared__ float part[4][64];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int col = blockIdx.x * 64 + tx;
+    const int r0 = blockIdx.y * kReduceRows;
+    const int r1 = min(rows, r0 + kReduceRows);
+    float acc = 0.f;
+    if (col < kMlpParams)
+        for (int r = r0 + ty; r < r1; r += 4) acc += partial[int64_t(r) * kMlpParams + col];
+    part[ty][tx] = acc;
+    __syncthreads();
+    if (ty == 0 && col < kMlpParams) atomicAdd(out + col, (part[0][tx] + part[1][tx]) + (part[2][tx] + part[3][tx]));
 }
 
 int backward_partial_rows(int n_groups) { return n_groups * kBwdWaves; }
@@ -670,7 +692,8 @@ hipError_t launch_backward(const BackwardArgs& a, int n_groups, hipStream_t s) {
 }
 
 hipError_t launch_reduce_mlp(const float* partial, int rows, float* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_rows, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, partial, rows, out);
+    const dim3 grid((kMlpParams + 63) / 64, (rows + kReduceRows - 1) / kReduceRows);
+    hipLaunchKernelGGL(k_reduce_rows, grid, dim3(256), 0, s, partial, rows, out);
     return hipGetLastError();
 }
 

@@ -51,31 +51,37 @@ __device__ __forceinline__ bool corner_live(int c, const int32_t fr[3]) {
     return ((c & 1) == 0 || fr[0] != 0) && ((c & 2) == 0 || fr[1] != 0) && ((c & 4) == 0 || fr[2] != 0);
 }
 
-// Gather at padded cell p (each in [0, B]) of a uint8 block.  The corners
-// (x, x+1) of each of the four (y, z) rows are 16 adjacent bytes, so the
-// 8 corners arrive in four 16-byte loads issued together.
-__device__ __forceinline__ void gather_u8(const uint8_t* __restrict__ blk, int Bp, const int32_t p[3],
-                                          const int32_t fr[3], Sample& smp) {
-    const uint8_t* base = blk + (int64_t((p[2] * Bp + p[1]) * Bp + p[0]) << 3);
+// The 8 corners of a padded cell of a uint8 block: the corners (x, x+1) of
+// each of the four (y, z) rows are 16 adjacent bytes, so four 16-byte loads
+// issued together bring all of them.
+struct Corners8 {
+    u32x4 row[4];
+};
+
+__device__ __forceinline__ void load_corners_u8(const uint8_t* __restrict__ cell, int Bp, Corners8& cn) {
     const int sy = Bp * 8, sz = Bp * Bp * 8;
-    const u32x4 q0 = ld_pair(base), q1 = ld_pair(base + sy);
-    const u32x4 q2 = ld_pair(base + sz), q3 = ld_pair(base + sz + sy);
+    cn.row[0] = ld_pair(cell);
+    cn.row[1] = ld_pair(cell + sy);
+    cn.row[2] = ld_pair(cell + sz);
+    cn.row[3] = ld_pair(cell + sz + sy);
+}
+
+// Trilinear sample from loaded uint8 corners.  Every non-zero weight is a
+// product of fractions >= 2^-16 (no underflow) and densities are
+// non-negative, so "some corner has non-zero density and non-zero weight"
+// is exactly "the FP32 density sum is positive".
+__device__ __forceinline__ void interp_u8(const Corners8& cn, const int32_t fr[3], Sample& smp) {
     uint2 v[8];
-    v[0] = make_uint2(q0.x, q0.y);
-    v[1] = make_uint2(q0.z, q0.w);
-    v[2] = make_uint2(q1.x, q1.y);
-    v[3] = make_uint2(q1.z, q1.w);
-    v[4] = make_uint2(q2.x, q2.y);
-    v[5] = make_uint2(q2.z, q2.w);
-    v[6] = make_uint2(q3.x, q3.y);
-    v[7] = make_uint2(q3.z, q3.w);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        v[2 * r] = make_uint2(cn.row[r].x, cn.row[r].y);
+        v[2 * r + 1] = make_uint2(cn.row[r].z, cn.row[r].w);
+    }
     float w[8];
     corner_weights(fr, w);
     float sd = 0.f, r0 = 0.f, r1 = 0.f, r2 = 0.f, f0 = 0.f, f1 = 0.f, f2 = 0.f, f3 = 0.f;
-    bool act = false;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-        act |= ((v[c].x & 0xFFu) != 0u) && corner_live(c, fr);
         sd += w[c] * ubyte(v[c].x, 0);
         r0 += w[c] * ubyte(v[c].x, 1);
         r1 += w[c] * ubyte(v[c].x, 2);
@@ -88,7 +94,15 @@ __device__ __forceinline__ void gather_u8(const uint8_t* __restrict__ blk, int B
     smp.sigma_raw = sd;
     smp.rgb[0] = r0; smp.rgb[1] = r1; smp.rgb[2] = r2;
     smp.feat[0] = f0; smp.feat[1] = f1; smp.feat[2] = f2; smp.feat[3] = f3;
-    smp.active = act;
+    smp.active = sd > 0.0f;
+}
+
+// Gather at padded cell p (each in [0, B]) of a uint8 block.
+__device__ __forceinline__ void gather_u8(const uint8_t* __restrict__ blk, int Bp, const int32_t p[3],
+                                          const int32_t fr[3], Sample& smp) {
+    Corners8 cn;
+    load_corners_u8(blk + (int64_t((p[2] * Bp + p[1]) * Bp + p[0]) << 3), Bp, cn);
+    interp_u8(cn, fr, smp);
 }
 
 // Gather at padded cell p of a float32 block (32 bytes per voxel).

@@ -37,11 +37,24 @@ __device__ __forceinline__ void march_composite(const RenderArgs& a, const uint2
     const float kx = g.sigma_scale * cs / float(g.N);
     const float t_stop = a.opts.t_stop;
     const bool early = a.opts.early_stop != 0;
+    // Consecutive samples often fall in the same cell (the step is half a
+    // voxel): its corners are then reused instead of loaded again.
+    const uint8_t* cached = nullptr;
+    Corners8 cn;
     march_ray(
         g, occ, o, s, [](int32_t, bool) {}, [](int32_t) {},
         [&](int64_t, int32_t, const uint8_t* vox, const int32_t p[3], const int32_t fr[3]) {
             Sample smp;
-            if (VT == 0) gather_u8(vox, g.Bp, p, fr, smp); else gather_f32(vox, g.Bp, p, fr, smp);
+            if (VT == 0) {
+                const uint8_t* cell = vox + (int64_t((p[2] * g.Bp + p[1]) * g.Bp + p[0]) << 3);
+                if (cell != cached) {
+                    load_corners_u8(cell, g.Bp, cn);
+                    cached = cell;
+                }
+                interp_u8(cn, fr, smp);
+            } else {
+                gather_f32(vox, g.Bp, p, fr, smp);
+            }
             if (!smp.active) return false;
             composite(st, smp, kx, cs);
             return early && st.T < t_stop;
