@@ -142,12 +142,23 @@ __host__ __device__ __forceinline__ int32_t block_rank(const uint2* occ, int32_t
 // j*smax in Q16, so the cell index by at most ceil(j*smax / 2^16), and all
 // j with j*smax <= (d-1) 2^16 land in inactive cells.  Returns that largest
 // j plus one (the current sample is inactive too).
+// (d <= 255 and smax <= 2^15, so m stays far below 2^24 and the products
+// below 2^32: the masks only tell the compiler that 24-bit multiplies do.)
 __host__ __device__ __forceinline__ int32_t skip_steps(int32_t d, int32_t smax, float inv_smax) {
-    const int32_t D = (d - 1) << 16;
-    int32_t m = (int32_t)__builtin_floorf((float)D * inv_smax);
-    if ((m + 1) * smax <= D) ++m;
-    if (m > 0 && m * smax > D) --m;
-    return m + 1;
+    const uint32_t D = uint32_t(d - 1) << 16;
+    const uint32_t sm = uint32_t(smax) & 0xFFFFFFu;
+    uint32_t m = uint32_t(__builtin_floorf((float)D * inv_smax)) & 0xFFFFFFu;
+    if (((m + 1) & 0xFFFFFFu) * sm <= D) ++m;
+    m &= 0xFFFFFFu;
+    if (m > 0 && m * sm > D) --m;
+    return int32_t(m) + 1;
+}
+
+// Linear index of cell p (each coordinate in [0, n)) of an n^3 array, nn = n*n;
+// all operands fit 24 bits.
+__host__ __device__ __forceinline__ uint32_t cell_index(const int32_t p[3], uint32_t n, uint32_t nn) {
+    return (uint32_t(p[2]) & 0x3FFu) * (nn & 0xFFFFFFu) + (uint32_t(p[1]) & 0x3FFu) * (n & 0xFFFFu) +
+           (uint32_t(p[0]) & 0x3FFu);
 }
 
 // Visits, in order, every lattice sample of a ray that lies in an occupied
@@ -157,6 +168,8 @@ __host__ __device__ __forceinline__ int32_t skip_steps(int32_t d, int32_t smax, 
 // 16-bit fractions, and returns true to stop the march.  on_block(lin, occ)
 // and on_inblock(n) (n samples inside an occupied block passed) feed the
 // visit trace.  `occ` is the occupancy table (usually staged in LDS).
+// Sample indices run relative to the ray's first lattice index inside the
+// grid (a ray has at most ~3.5 N samples there); callbacks get absolute k.
 // Returns the k at which on_sample stopped the march, or -1.
 template <typename OnBlock, typename OnInBlock, typename OnSample>
 __host__ __device__ __forceinline__ int64_t march_ray(const GridArgs& g, const uint2* occ, const int64_t o[3],
@@ -164,6 +177,7 @@ __host__ __device__ __forceinline__ int64_t march_ray(const GridArgs& g, const u
                                                       OnInBlock&& on_inblock, OnSample&& on_sample) {
     const int bs = 16 + g.logB;
     const int64_t L = int64_t(g.N) << 16;
+    const uint32_t nc = uint32_t(g.Bc), ncc = nc * nc;
     int64_t klo, khi;
     if (!entry_range(o, s, L, klo, khi)) return -1;
     float inv[3];
@@ -177,8 +191,9 @@ __host__ __device__ __forceinline__ int64_t march_ray(const GridArgs& g, const u
         P[a] = int32_t(o[a] + klo * int64_t(s[a]));  // inside [0, N 2^16)
     }
     const float inv_smax = 1.0f / float(smax);
-    int64_t k = klo;
-    while (k <= khi) {
+    const int32_t kend = int32_t(khi - klo);  // relative, inclusive
+    int32_t k = 0;
+    while (k <= kend) {
         int32_t b[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) b[a] = P[a] >> bs;
@@ -192,7 +207,7 @@ __host__ __device__ __forceinline__ int64_t march_ray(const GridArgs& g, const u
                              ((P[1] + (nstep - 1) * s[1]) >> bs) != b[1] ||
                              ((P[2] + (nstep - 1) * s[2]) >> bs) != b[2]))
             --nstep;
-        const int64_t kn = (k + int64_t(nstep)) < (khi + 1) ? (k + int64_t(nstep)) : (khi + 1);
+        const int32_t kn = (k + nstep) < (kend + 1) ? (k + nstep) : (kend + 1);
         const int32_t lin = (b[2] * g.G + b[1]) * g.G + b[0];
         const int32_t r = block_rank(occ, lin, g.n_blocks);
         on_block(lin, r >= 0);
@@ -202,16 +217,16 @@ __host__ __device__ __forceinline__ int64_t march_ray(const GridArgs& g, const u
             int32_t q[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) q[a] = P[a] - (b[a] << bs) + 32768;  // padded Q16 coordinate
-            int32_t left = int32_t(kn - k);
-            int64_t kk = k;
+            int32_t left = kn - k;
+            int32_t kk = k;
             while (left > 0) {
                 const int32_t p[3] = {q[0] >> 16, q[1] >> 16, q[2] >> 16};
-                const int32_t d = dist[(p[2] * g.Bc + p[1]) * g.Bc + p[0]];
+                const int32_t d = dist[cell_index(p, nc, ncc)];
                 int32_t adv = 1;
                 if (d == 0) {
                     on_inblock(1);
                     const int32_t fr[3] = {q[0] & 0xFFFF, q[1] & 0xFFFF, q[2] & 0xFFFF};
-                    if (on_sample(kk, r, vox, p, fr)) return kk;
+                    if (on_sample(klo + kk, r, vox, p, fr)) return klo + kk;
                 } else {
                     adv = skip_steps(d, smax, inv_smax);
                     adv = adv < left ? adv : left;
@@ -223,14 +238,13 @@ __host__ __device__ __forceinline__ int64_t march_ray(const GridArgs& g, const u
                 for (int a = 0; a < 3; ++a) q[a] += adv * s[a];
             }
         }
-        const int32_t adv = int32_t(kn - k);
+        const int32_t adv = kn - k;
 #pragma unroll
         for (int a = 0; a < 3; ++a) P[a] += adv * s[a];  // |adv s| <= B 2^16 + |s|
         k = kn;
     }
     return -1;
 }
-
 
 // The same visit sequence as march_ray, with both loops made convergent
 // across the wavefront: every lane runs one macroblock step per outer trip
@@ -244,6 +258,7 @@ __device__ __forceinline__ void march_ray_sync(const GridArgs& g, const uint2* o
                                                const int32_t s[3], OnSample&& on_sample, OnSync&& on_sync) {
     const int bs = 16 + g.logB;
     const int64_t L = int64_t(g.N) << 16;
+    const uint32_t nc = uint32_t(g.Bc), ncc = nc * nc;
     int64_t klo = 0, khi = -1;
     if (live) live = entry_range(o, s, L, klo, khi);
     float inv[3];
@@ -257,11 +272,12 @@ __device__ __forceinline__ void march_ray_sync(const GridArgs& g, const uint2* o
         P[a] = live ? int32_t(o[a] + klo * int64_t(s[a])) : 0;
     }
     const float inv_smax = 1.0f / float(smax);
-    int64_t k = klo;
+    const int32_t kend = live ? int32_t(khi - klo) : -1;
+    int32_t k = 0;
     for (;;) {
-        live = live && k <= khi;
+        live = live && k <= kend;
         if (!__any(live)) break;
-        int64_t kn = k, kk = k;
+        int32_t kn = k, kk = k;
         int32_t left = 0, r = -1;
         int32_t q[3] = {0, 0, 0};
         const uint8_t* __restrict__ dist = g.rec;
@@ -277,25 +293,25 @@ __device__ __forceinline__ void march_ray_sync(const GridArgs& g, const uint2* o
                                      ((P[1] + (nstep - 1) * s[1]) >> bs) != b[1] ||
                                      ((P[2] + (nstep - 1) * s[2]) >> bs) != b[2]))
                     --nstep;
-                kn = (k + int64_t(nstep)) < (khi + 1) ? (k + int64_t(nstep)) : (khi + 1);
+                kn = (k + nstep) < (kend + 1) ? (k + nstep) : (kend + 1);
                 const int32_t lin = (b[2] * g.G + b[1]) * g.G + b[0];
                 r = block_rank(occ, lin, g.n_blocks);
                 if (r >= 0) {
                     dist = g.rec + int64_t(r) * g.rec_stride;
 #pragma unroll
                     for (int a = 0; a < 3; ++a) q[a] = P[a] - (b[a] << bs) + 32768;
-                    left = int32_t(kn - k);
+                    left = kn - k;
                 }
             }
         }
         while (__any(left > 0)) {
             if (left > 0) {
                 const int32_t p[3] = {q[0] >> 16, q[1] >> 16, q[2] >> 16};
-                const int32_t d = dist[(p[2] * g.Bc + p[1]) * g.Bc + p[0]];
+                const int32_t d = dist[cell_index(p, nc, ncc)];
                 int32_t adv = 1;
                 if (d == 0) {
                     const int32_t fr[3] = {q[0] & 0xFFFF, q[1] & 0xFFFF, q[2] & 0xFFFF};
-                    if (on_sample(kk, r, dist + g.dist_bytes, p, fr)) {
+                    if (on_sample(klo + kk, r, dist + g.dist_bytes, p, fr)) {
                         live = false;
                         adv = left;
                     }
@@ -311,7 +327,7 @@ __device__ __forceinline__ void march_ray_sync(const GridArgs& g, const uint2* o
             on_sync();
         }
         if (live) {
-            const int32_t adv = int32_t(kn - k);
+            const int32_t adv = kn - k;
 #pragma unroll
             for (int a = 0; a < 3; ++a) P[a] += adv * s[a];
             k = kn;

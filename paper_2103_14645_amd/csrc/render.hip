@@ -41,12 +41,13 @@ __device__ __forceinline__ void march_composite(const RenderArgs& a, const uint2
     // voxel): its corners are then reused instead of loaded again.
     const uint8_t* cached = nullptr;
     Corners8 cn;
+    const uint32_t nb = uint32_t(g.Bp), nbb = nb * nb;
     march_ray(
         g, occ, o, s, [](int32_t, bool) {}, [](int32_t) {},
         [&](int64_t, int32_t, const uint8_t* vox, const int32_t p[3], const int32_t fr[3]) {
             Sample smp;
             if (VT == 0) {
-                const uint8_t* cell = vox + (int64_t((p[2] * g.Bp + p[1]) * g.Bp + p[0]) << 3);
+                const uint8_t* cell = vox + (uint64_t(cell_index(p, nb, nbb)) << 3);
                 if (cell != cached) {
                     load_corners_u8(cell, g.Bp, cn);
                     cached = cell;
@@ -100,6 +101,9 @@ __device__ __forceinline__ void render_ray(const RenderArgs& a, const uint2* occ
         int64_t o[3];
         int32_t s[3];
         ray_setup(a.cams[ci], a.grid.N, px, py, o, s, d);
+        // keep the direction as three floats from here on (left alone, the
+        // compiler carries its FP64 form through the march)
+        asm volatile("" : "+v"(d[0]), "+v"(d[1]), "+v"(d[2]));
         march_composite<VT>(a, occ, o, s, st);
     }
     float R[3] = {0.f, 0.f, 0.f};
