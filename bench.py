@@ -1,6 +1,6 @@
 """Throughput of the SNeRG render path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs plain,batched,adjoint,large]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs plain,batched,adjoint,large,finetune]
     python bench.py --legs plain,copy --no-cpu-baseline   # adds the copy-kernel calibration launches
     python bench.py --source-hash                          # hash of the render kernel sources
 
@@ -9,8 +9,11 @@ Headline (value): forward Mrays/s of the plain FP32 path on the 512^3 grid
 inputs resident in device memory; fps = value / 0.64.  Further legs, each
 timed the same way: the batched FP16-MFMA-MLP forward (1024^3 grid, 16
 cameras of mixed size in one persistent launch replayed from a HIP graph)
-with its max-abs error against the FP64 oracle, and the adjoint (8 views at
-800x800 on a float32 shadow of the 512^3 grid, forward + backward).
+with its max-abs error against the FP64 oracle, the adjoint (8 views at
+800x800 on a float32 shadow of the 512^3 grid, forward + backward), the
+large case (64 x 1920x1080 in one launch, then 65,536-ray minibatch forward
++ backward), and fine-tuning of the deferred network on the fixed uint8
+grid (render, squared error, MLP backward, Adam per 65,536-ray step).
 Prints one JSON line on stdout; progress goes to stderr.
 
 roofline.traffic is the measured HBM traffic of one render launch, read from
@@ -48,8 +51,10 @@ def render_source_hash():
 
 
 def measured_traffic():
-    """Bytes per launch from the committed counter summary, if it describes
-    the current kernel sources ("key = value" lines), else None."""
+    """(bytes per launch, copy GB/s) from the committed counter summary if it
+    describes the current kernel sources ("key = value" lines), else
+    (None, None).  The copy rate is the plain 1 GiB copy measured in the
+    same counter run: what this HBM delivers to a streaming kernel."""
     try:
         kv = {}
         for line in open(TRAFFIC_SUMMARY):
@@ -57,10 +62,10 @@ def measured_traffic():
                 k, v = line.split("=", 1)
                 kv[k.strip().strip("`")] = v.strip().strip("`")
         if kv.get("render_source_sha256") != render_source_hash():
-            return None
-        return int(kv["traffic_bytes_per_launch"])
+            return None, None
+        return int(kv["traffic_bytes_per_launch"]), float(kv["copy_read_write_gbs"])
     except (OSError, KeyError, ValueError):
-        return None
+        return None, None
 
 
 def log(msg):
@@ -81,6 +86,35 @@ def time_launches(fn, steps, warmup, torch):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
+
+
+def launch_spread(fn, n, torch):
+    """p10 / p50 / p90 of n individually event-timed launches (ms)."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for e0, e1 in ev:
+        e0.record()
+        fn()
+        e1.record()
+    torch.cuda.synchronize()
+    t = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+    return [round(float(np.percentile(t, q)), 4) for q in (10, 50, 90)]
+
+
+def host_cpu():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_rate(O, og, mlp, cams, ids, threads):
+    """Oracle Mrays/s on the given ray ids with `threads` OpenMP threads."""
+    t0 = time.perf_counter()
+    out = O.render(og, mlp, cams, ray_ids=ids, threads=threads)["rgba"]
+    return out, len(ids) / (time.perf_counter() - t0) / 1e6
 
 
 def frame_counters(S, h, dg, cams):
@@ -117,9 +151,11 @@ def leg_plain(args, torch, S, W, O):
 
     log(f"plain512: {g.n_blocks} blocks ({g.meta['occupancy']:.3f}), {n} rays; warmup {args.warmup}, steps {args.steps}")
     ms = time_launches(step, args.steps, args.warmup, torch)
+    spread = launch_spread(step, args.steps, torch)
     cnt = frame_counters(S, h, dg, cams)
     abytes = algorithmic_bytes(cnt)
-    res = dict(ms=ms, rays=n, mrays=n / ms / 1e3, counters=cnt, alg_bytes=abytes, out=out, cams=cams, g=g, mlp=mlp)
+    res = dict(ms=ms, rays=n, mrays=n / ms / 1e3, counters=cnt, alg_bytes=abytes, out=out, cams=cams, g=g, mlp=mlp,
+               spread=spread)
     log(f"plain512: {ms:.3f} ms/frame, {res['mrays']:.1f} Mrays/s, {abytes / ms / 1e6:.1f} GB/s algorithmic")
     return res
 
@@ -146,9 +182,10 @@ def leg_batched(args, torch, S, W, O):
     ms = time_launches(step, steps, max(1, args.warmup), torch)
     frame = out.cpu().numpy()
     ids = np.sort(np.random.default_rng(3).choice(n, 4096, replace=False))
-    ref = O.render(O.OracleGrid(g), mlp, cams, ray_ids=ids)["rgba"]
+    ref, cpu_mrays = oracle_rate(O, O.OracleGrid(g), mlp, cams, ids, args.cpu_threads)
     err = float(np.abs(frame[ids] - ref).max())
-    res = dict(ms=ms, rays=n, mrays=n / ms / 1e3, max_abs_err=err, err_sample=len(ids), tuning=list(best))
+    res = dict(ms=ms, rays=n, mrays=n / ms / 1e3, max_abs_err=err, err_sample=len(ids), tuning=list(best),
+               cpu_mrays=cpu_mrays)
     log(f"batched1024: {ms:.3f} ms/batch, {res['mrays']:.1f} Mrays/s, fp16 max-abs err {err:.2e}")
     return res
 
@@ -215,7 +252,7 @@ def leg_large(args, torch, S, W, O):
     ms = time_launches(step, 2, 1, torch)
     ids = torch.from_numpy(np.sort(np.random.default_rng(3).choice(n, 4096, replace=False))).cuda()
     frame = out[ids].cpu().numpy()
-    ref = O.render(O.OracleGrid(g), mlp, cams, ray_ids=ids.cpu().numpy())["rgba"]
+    ref, cpu_mrays = oracle_rate(O, O.OracleGrid(g), mlp, cams, ids.cpu().numpy(), args.cpu_threads)
     err = float(np.abs(frame - ref).max())
     del out
     # backward on minibatches of 65,536 rays
@@ -251,10 +288,48 @@ def leg_large(args, torch, S, W, O):
     ms_step = time_launches(train_step, 8, 2, torch)
     ms_f = time_launches(fwd_only, 8, 2, torch)
     ms_b = max(ms_step - ms_f, 1e-6)
-    res = dict(ms=ms, rays=n, mrays=n / ms / 1e3, max_abs_err=err, tuning=list(best), mb=mb,
+    res = dict(ms=ms, rays=n, mrays=n / ms / 1e3, max_abs_err=err, tuning=list(best), mb=mb, cpu_mrays=cpu_mrays,
                ms_train_step=ms_step, ms_mb_fwd=ms_f, bwd_mrays=mb / ms_b / 1e3)
     log(f"large1024: {ms:.1f} ms/launch, {res['mrays']:.1f} Mrays/s, fp16 err {err:.2e}; minibatch fwd+bwd "
         f"{ms_step:.2f} ms (bwd {res['bwd_mrays']:.1f} Mrays/s)")
+    return res
+
+
+def leg_finetune(args, torch, S, W):
+    """Fine-tuning of the deferred network on the fixed 512^3 uint8 SNeRG
+    (Section 5.5): 65,536-ray minibatches over the 8 adjoint views, targets
+    rendered with the original weights, training from perturbed weights;
+    each step is render + squared error + MLP backward + Adam."""
+    from paper_2103_14645_amd import finetune as F
+    cfg = W.config("adjoint512")
+    g, cams, mlp = cfg["grid"], cfg["cams"], cfg["mlp"]
+    h = S.Handle()
+    dg = S.DeviceGrid(h, g.N, g.B, g.indirection, g.dens, g.rgb, g.feat)
+    n = sum(c.n_rays for c in cams)
+    target = torch.empty((n, 4), device="cuda")
+    S.snerg_render(h, dg.struct(), S.mlp_tensor(mlp), S.make_cameras(cams), None, n, S.make_opts(), target)
+    start, _ = W.perturbed(mlp, g, rel=0.3)
+    w = S.mlp_tensor(start)
+    mb = 65536
+    ft = F.MlpFineTuner(h, dg.struct(), w, cams, target, lr=3e-4, max_batch=mb)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(3)
+    order = torch.randperm(n, device="cuda", generator=gen)
+    batches = [order[i * mb:(i + 1) * mb] for i in range(n // mb)]
+    it = [0]
+    losses = []
+
+    def step():
+        losses.append(ft.step(batches[it[0] % len(batches)]))
+        it[0] += 1
+
+    steps = max(4, args.steps)
+    ms = time_launches(step, steps, 2, torch)
+    ls = [float(x.item()) for x in losses]
+    res = dict(ms_step=ms, steps_per_s=1000.0 / ms, mrays=mb / ms / 1e3, minibatch=mb, rays_total=n,
+               loss_first=ls[0], loss_last=ls[-1], steps_run=len(ls))
+    log(f"finetune: {ms:.3f} ms/step ({res['steps_per_s']:.0f} steps/s, {res['mrays']:.1f} Mrays/s), "
+        f"loss {ls[0]:.5f} -> {ls[-1]:.5f} over {len(ls)} steps")
     return res
 
 
@@ -273,18 +348,20 @@ def leg_copy(torch):
     return dict(ms=ms, bytes=COPY_BYTES, gbs=2 * COPY_BYTES / ms / 1e6)
 
 
-def cpu_baseline(plain, O):
-    """The FP64 oracle on the host cores over the whole 800x800 frame."""
+def cpu_baseline(plain, O, threads):
+    """The FP64 oracle on the host: all `threads` over the whole 800x800
+    frame, and one thread over every 16th ray of it."""
     n = plain["rays"]
     ids = np.arange(0, n, dtype=np.int64)
     og = O.OracleGrid(plain["g"])
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
     ref = O.render(og, plain["mlp"], plain["cams"], ray_ids=ids, threads=threads)["rgba"]
     dt = time.perf_counter() - t0
     err = float(np.abs(plain["out"].cpu().numpy()[ids] - ref).max())
+    _, one = oracle_rate(O, og, plain["mlp"], plain["cams"], ids[::16], 1)
     return dict(value=len(ids) / dt / 1e6, unit="Mrays/s", cores=threads, kind="oracle",
                 sample=f"all {len(ids)} rays of the 800x800 frame, {dt:.1f} s wall on {threads} threads",
+                single_thread_mrays=round(one, 4), host=host_cpu(), nproc=os.cpu_count(),
                 gpu_max_abs_err=err)
 
 
@@ -293,9 +370,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--legs", default="plain,batched,adjoint,large")
+    ap.add_argument("--legs", default="plain,batched,adjoint,large,finetune")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--source-hash", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
     args = ap.parse_args()
     if args.source_hash:
         print(render_source_hash())
@@ -320,11 +398,14 @@ def main():
         extra["adjoint_512"] = leg_adjoint(args, torch, S, W, O)
     if "large" in legs:
         extra["large_1024"] = leg_large(args, torch, S, W, O)
+    if "finetune" in legs:
+        extra["finetune"] = leg_finetune(args, torch, S, W)
     if "copy" in legs:
         extra["copy"] = leg_copy(torch)
 
     ms = plain["ms"]
     achieved = plain["alg_bytes"] / (ms * 1e-3) / 1e9
+    traffic, copy_gbs = measured_traffic()
     line = {
         "metric": "Mrays/s and fps at 800x800 (fwd, batched FP16-MLP vs plain FP32); bwd Mrays/s",
         "value": round(plain["mrays"], 3),
@@ -340,9 +421,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": "plain512: 512^3 SNeRG, B=32, 10.6% occupied procedural shell, uint8 atlas, "
                                "one 800x800 camera (39 deg), FP32 34-16-16-3 MLP",
-                   "fps_800x800": round(1000.0 / ms, 2), "rays": plain["rays"]},
+                   "fps_800x800": round(1000.0 / ms, 2), "rays": plain["rays"],
+                   "launch_ms_p10_p50_p90": plain["spread"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_gbs": round(traffic / (ms * 1e-3) / 1e9, 1) if traffic else None,
+                     "traffic_frac_of_copy_bw": round(traffic / (ms * 1e-3) / 1e9 / copy_gbs, 4) if traffic else None,
                      "kernel": "k_render<u8, fp32-mlp>", "alg_bytes_per_launch": plain["alg_bytes"],
                      "counters": plain["counters"]},
     }
@@ -352,7 +436,8 @@ def main():
         legs_out["batched_fp16_1024"] = {"mrays": round(b["mrays"], 3), "ms": round(b["ms"], 4),
                                          "fps_800x800_equiv": round(b["mrays"] / 0.64, 2),
                                          "max_abs_err_vs_oracle": b["max_abs_err"], "err_sample": b["err_sample"],
-                                         "rays": b["rays"], "tuning": b["tuning"]}
+                                         "rays": b["rays"], "tuning": b["tuning"],
+                                         "cpu_oracle_mrays": round(b["cpu_mrays"], 4)}
     if "adjoint_512" in extra:
         a = extra["adjoint_512"]
         legs_out["adjoint_512"] = {"bwd_mrays": round(a["bwd_mrays"], 3), "fwd_mrays": round(a["fwd_mrays"], 3),
@@ -365,13 +450,16 @@ def main():
                                   "max_abs_err_vs_oracle": b["max_abs_err"], "rays": b["rays"],
                                   "tuning": b["tuning"], "minibatch": b["mb"],
                                   "ms_minibatch_fwd_bwd": round(b["ms_train_step"], 4),
-                                  "bwd_mrays": round(b["bwd_mrays"], 3)}
+                                  "bwd_mrays": round(b["bwd_mrays"], 3), "cpu_oracle_mrays": round(b["cpu_mrays"], 4)}
+    if "finetune" in extra:
+        f = extra["finetune"]
+        legs_out["finetune_mlp_512"] = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in f.items()}
     if "copy" in extra:
         legs_out["copy_calibration"] = {k: round(v, 4) for k, v in extra["copy"].items()}
     line["legs"] = legs_out
     if not args.no_cpu_baseline:
         log("cpu baseline (FP64 oracle)")
-        line["cpu_baseline"] = cpu_baseline(plain, O)
+        line["cpu_baseline"] = cpu_baseline(plain, O, args.cpu_threads)
     print(json.dumps(line), flush=True)
 
 

@@ -90,6 +90,7 @@ extern "C" {
 #define SNERG_FLAG_MLP_FP16 (1u << 0)   /* deferred MLP on FP16 MFMA tiles, FP32 accumulation */
 #define SNERG_FLAG_PERSISTENT (1u << 1) /* one persistent launch over a global tile queue */
 #define SNERG_FLAG_GRAPH (1u << 2)      /* replay the launch from a captured HIP graph */
+#define SNERG_FLAG_MLP_GRAD_ONLY (1u << 3) /* backward: MLP gradient only (any grid dtype) */
 
 #define SNERG_MLP_PARAMS 883 /* W1[16][34] b1[16] W2[16][16] b2[16] W3[3][16] b3[3], [out][in] */
 
@@ -186,6 +187,9 @@ int snerg_render(snerg_handle *h, const snerg_grid *grid, const float *mlp, cons
  * grad_feat in canonical atlas layout.  Gradient sums use float32 atomics,
  * so their rounding depends on scheduling.  With SNERG_FLAG_MLP_FP16 the MLP
  * backward runs on FP16 MFMA tiles with FP32 accumulation (as the forward).
+ * With SNERG_FLAG_MLP_GRAD_ONLY only grad_mlp is computed (the fine-tuning
+ * of Section 5.5 optimises the deferred network alone): no ray is
+ * re-marched, the grid may be SNERG_U8 and grad_dens/rgb/feat may be NULL.
  */
 int snerg_render_backward(snerg_handle *h, const snerg_grid *grid, const float *mlp,
                           const snerg_camera *cams, int32_t n_cams, const int64_t *ray_ids,
@@ -207,6 +211,39 @@ int snerg_trace_visits(snerg_handle *h, const snerg_grid *grid, const snerg_came
                        int32_t n_cams, const int64_t *ray_ids, int64_t n_rays, const snerg_opts *opts,
                        int32_t max_visits, int32_t *visits, int32_t *counts, int32_t *counters,
                        void *stream);
+
+/* ----------------------------------------------------------- fine-tuning */
+
+/*
+ * Squared error of rendered against observed pixels, the loss of the
+ * fine-tuning in Section 5.5: loss = (1 / 3n) sum over rays and RGB of
+ * (rgba - target)^2, and its gradient grad_rgba = (2 / 3n) (rgba - target)
+ * for RGB, 0 for alpha (the observed images carry no alpha).  rgba,
+ * grad_rgba: device float32 [n][4]; target: device float32 [rows][4], row i
+ * of rgba compared with row target_ids[i] (device int64 [n], each in
+ * [0, rows), unchecked) or, with target_ids NULL, row i; loss: device
+ * float32 [1] (overwritten).  n may be 0 (loss 0).
+ */
+int snerg_loss_mse(snerg_handle *h, const float *rgba, const float *target, const int64_t *target_ids,
+                   int64_t n, float *grad_rgba, float *loss, void *stream);
+
+typedef struct {
+    float lr;     /* Section 5.5 uses 3e-4 */
+    float beta1;  /* 0.9 */
+    float beta2;  /* 0.999 */
+    float eps;    /* 1e-8 */
+    int32_t step; /* t >= 1: this update's index, for the bias corrections */
+    int32_t reserved;
+} snerg_adam;
+
+/*
+ * One Adam update (Kingma and Ba, Algorithm 1), the optimiser of Section
+ * 5.5, applied elementwise: m <- b1 m + (1 - b1) g, v <- b2 v + (1 - b2) g^2,
+ * p <- p - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).  param, m, v
+ * (updated in place) and grad: device float32 [n]; m and v start at zero.
+ */
+int snerg_adam_step(snerg_handle *h, float *param, const float *grad, float *m, float *v, int64_t n,
+                    const snerg_adam *cfg, void *stream);
 
 /* ---------------------------------------------------------------- tuning */
 

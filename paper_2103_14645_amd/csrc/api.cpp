@@ -90,7 +90,7 @@ int check_opts(const snerg_opts* o) {
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(o->bg[a])) return fail(SNERG_ERR_INVALID_ARG, "opts->bg must be finite");
     if (!std::isfinite(o->t_stop) || o->t_stop < 0.0f) return fail(SNERG_ERR_INVALID_ARG, "opts->t_stop must be finite and >= 0");
-    const uint32_t known = SNERG_FLAG_MLP_FP16 | SNERG_FLAG_PERSISTENT | SNERG_FLAG_GRAPH;
+    const uint32_t known = SNERG_FLAG_MLP_FP16 | SNERG_FLAG_PERSISTENT | SNERG_FLAG_GRAPH | SNERG_FLAG_MLP_GRAD_ONLY;
     if (o->flags & ~known) return fail(SNERG_ERR_UNSUPPORTED, "unknown opts->flags bits");
     return SNERG_OK;
 }
@@ -434,9 +434,13 @@ int snerg_render_backward(snerg_handle* h, const snerg_grid* grid, const float* 
     if (n_rays < 0) return fail(SNERG_ERR_INVALID_ARG, "n_rays must be >= 0");
     int rc = common_render_checks(grid, mlp, true, cams, n_cams, ray_ids, n_rays, opts, &total);
     if (rc) return rc;
-    if (grid->dtype != SNERG_F32) return fail(SNERG_ERR_UNSUPPORTED, "the backward pass needs a SNERG_F32 grid");
+    const bool mlp_only = (opts->flags & SNERG_FLAG_MLP_GRAD_ONLY) != 0;
+    if (!mlp_only && grid->dtype != SNERG_F32)
+        return fail(SNERG_ERR_UNSUPPORTED, "grid gradients need a SNERG_F32 grid");
     if (!aux || !grad_rgba) return fail(SNERG_ERR_INVALID_ARG, "aux/grad_rgba is NULL");
-    if (!grad_mlp || !grad_dens || !grad_rgb || !grad_feat) return fail(SNERG_ERR_INVALID_ARG, "a gradient output is NULL");
+    if (!grad_mlp) return fail(SNERG_ERR_INVALID_ARG, "grad_mlp is NULL");
+    if (!mlp_only && (!grad_dens || !grad_rgb || !grad_feat))
+        return fail(SNERG_ERR_INVALID_ARG, "a grid gradient output is NULL");
     if (!h) return fail(SNERG_ERR_INVALID_ARG, "handle is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t B3 = int64_t(grid->B) * grid->B * grid->B;
@@ -454,9 +458,11 @@ int snerg_render_backward(snerg_handle* h, const snerg_grid* grid, const float* 
     int64_t total_tiles = 0;
     rc = upload_cams(h, cams, n_cams, h->tuning.tile_w, h->tuning.tile_h, s, &total_tiles);
     if (rc) return rc;
-    HIP_TRY(launch_fill_f32(grad_dens, nv, 0.0f, s));
-    HIP_TRY(launch_fill_f32(grad_rgb, nv * 3, 0.0f, s));
-    HIP_TRY(launch_fill_f32(grad_feat, nv * 4, 0.0f, s));
+    if (!mlp_only) {
+        HIP_TRY(launch_fill_f32(grad_dens, nv, 0.0f, s));
+        HIP_TRY(launch_fill_f32(grad_rgb, nv * 3, 0.0f, s));
+        HIP_TRY(launch_fill_f32(grad_feat, nv * 4, 0.0f, s));
+    }
     HIP_TRY(launch_fill_f32(grad_mlp, kMlpParams, 0.0f, s));
     if (n_rays == 0) return SNERG_OK;
     BackwardArgs a;
@@ -479,8 +485,38 @@ int snerg_render_backward(snerg_handle* h, const snerg_grid* grid, const float* 
     a.total_tiles = total_tiles;
     a.tile_w = h->tuning.tile_w;
     a.tile_h = h->tuning.tile_h;
+    a.mlp_only = mlp_only ? 1 : 0;
     HIP_TRY(launch_backward(a, n_groups, s));
     if (mlp_mode != kMlpOff) HIP_TRY(launch_reduce_mlp(h->d_partial, rows, grad_mlp, s));
+    return SNERG_OK;
+}
+
+int snerg_loss_mse(snerg_handle* h, const float* rgba, const float* target, const int64_t* target_ids, int64_t n,
+                   float* grad_rgba, float* loss, void* stream) {
+    if (n < 0) return fail(SNERG_ERR_INVALID_ARG, "n must be >= 0");
+    if (!loss) return fail(SNERG_ERR_INVALID_ARG, "loss is NULL");
+    if (n > 0 && (!rgba || !target || !grad_rgba)) return fail(SNERG_ERR_INVALID_ARG, "rgba/target/grad_rgba is NULL");
+    if (!h) return fail(SNERG_ERR_INVALID_ARG, "handle is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(launch_mse(rgba, target, target_ids, n, grad_rgba, loss, s));
+    return SNERG_OK;
+}
+
+int snerg_adam_step(snerg_handle* h, float* param, const float* grad, float* m, float* v, int64_t n,
+                    const snerg_adam* cfg, void* stream) {
+    if (n < 0) return fail(SNERG_ERR_INVALID_ARG, "n must be >= 0");
+    if (!cfg) return fail(SNERG_ERR_INVALID_ARG, "cfg is NULL");
+    if (cfg->step < 1) return fail(SNERG_ERR_INVALID_ARG, "cfg->step must be >= 1");
+    if (!std::isfinite(cfg->lr) || !std::isfinite(cfg->eps) || cfg->eps <= 0.0f)
+        return fail(SNERG_ERR_INVALID_ARG, "cfg->lr must be finite and cfg->eps > 0");
+    if (!(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f && cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f))
+        return fail(SNERG_ERR_INVALID_ARG, "cfg->beta1/beta2 must lie in [0, 1)");
+    if (n > 0 && (!param || !grad || !m || !v)) return fail(SNERG_ERR_INVALID_ARG, "param/grad/m/v is NULL");
+    if (!h) return fail(SNERG_ERR_INVALID_ARG, "handle is NULL");
+    const float c1 = float(1.0 - std::pow(double(cfg->beta1), double(cfg->step)));
+    const float c2 = float(1.0 - std::pow(double(cfg->beta2), double(cfg->step)));
+    HIP_TRY(launch_adam(param, grad, m, v, n, cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, c1, c2,
+                        static_cast<hipStream_t>(stream)));
     return SNERG_OK;
 }
 

@@ -673,6 +673,7 @@ hipError_t launch_backward(const BackwardArgs& a, int n_groups, hipStream_t s) {
         hipLaunchKernelGGL(k_mlp_backward<false>, dim3(n_groups), dim3(64 * kBwdWaves), 0, s, a);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+    if (a.mlp_only) return hipSuccess;
     // aggregation keys are int32 voxel indices
     const int64_t n_vox = int64_t(a.grid.n_blocks) * a.grid.B * a.grid.B * a.grid.B;
     const bool agg = !a.ray_ids && n_vox < (int64_t(1) << 31);

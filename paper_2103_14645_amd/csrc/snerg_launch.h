@@ -56,6 +56,7 @@ struct BackwardArgs {
     float* grad_feat;
     int64_t total_tiles;   // tile_w x tile_h tiles over all cameras (no ray list)
     int32_t tile_w, tile_h;
+    int32_t mlp_only;      // MLP gradient only: no re-march
 };
 
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
@@ -70,6 +71,10 @@ hipError_t launch_render(const RenderArgs& a, int vt, int mlp_mode, int waves_pe
 hipError_t launch_trace(const RenderArgs& a, int vt, hipStream_t s);
 hipError_t launch_backward(const BackwardArgs& a, int n_groups, hipStream_t s);
 int backward_partial_rows(int n_groups);
+hipError_t launch_mse(const float* rgba, const float* target, const int64_t* ids, int64_t n, float* grad, float* loss,
+                      hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2, hipStream_t s);
 hipError_t launch_reduce_mlp(const float* partial, int n_groups, float* out, hipStream_t s);
 
 }  // namespace snerg

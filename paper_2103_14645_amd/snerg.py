@@ -36,6 +36,7 @@ SNERG_F32 = 1
 SNERG_FLAG_MLP_FP16 = 1 << 0
 SNERG_FLAG_PERSISTENT = 1 << 1
 SNERG_FLAG_GRAPH = 1 << 2
+SNERG_FLAG_MLP_GRAD_ONLY = 1 << 3
 
 SNERG_MLP_PARAMS = 883
 
@@ -61,6 +62,11 @@ class snerg_camera(ctypes.Structure):
 class snerg_opts(ctypes.Structure):
     _fields_ = [("bg", ctypes.c_float * 3), ("t_stop", ctypes.c_float), ("early_stop", ctypes.c_int32),
                 ("mlp_on", ctypes.c_int32), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
+
+
+class snerg_adam(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("step", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class snerg_tuning(ctypes.Structure):
@@ -94,6 +100,8 @@ def lib():
             "snerg_set_tuning": [_P, _P],
             "snerg_get_tuning": [_P, _P],
             "snerg_autotune": [_P, _P, _P, _P, i32, _P, _P, i32, i32, _P, _P, _P, _P],
+            "snerg_loss_mse": [_P, _P, _P, _P, i64, _P, _P, _P],
+            "snerg_adam_step": [_P, _P, _P, _P, _P, i64, _P, _P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -109,7 +117,7 @@ def lib():
 
 EXPORTED = ["snerg_create", "snerg_destroy", "snerg_status_string", "snerg_last_error", "snerg_packed_size",
             "snerg_pack_grid", "snerg_render", "snerg_render_backward", "snerg_trace_visits",
-            "snerg_set_tuning", "snerg_get_tuning", "snerg_autotune"]
+            "snerg_set_tuning", "snerg_get_tuning", "snerg_autotune", "snerg_loss_mse", "snerg_adam_step"]
 
 
 def _check(rc: int, what: str):
@@ -146,14 +154,14 @@ def make_cameras(cams):
 
 
 def make_opts(bg=(1.0, 1.0, 1.0), t_stop=1e-3, early_stop=True, mlp_on=True, fp16=False,
-              persistent=False, graph=False):
+              persistent=False, graph=False, mlp_grad_only=False):
     o = snerg_opts()
     o.bg[:] = [float(v) for v in bg]
     o.t_stop = float(t_stop)
     o.early_stop = int(bool(early_stop))
     o.mlp_on = int(bool(mlp_on))
     o.flags = ((SNERG_FLAG_MLP_FP16 if fp16 else 0) | (SNERG_FLAG_PERSISTENT if persistent else 0)
-               | (SNERG_FLAG_GRAPH if graph else 0))
+               | (SNERG_FLAG_GRAPH if graph else 0) | (SNERG_FLAG_MLP_GRAD_ONLY if mlp_grad_only else 0))
     return o
 
 
@@ -199,6 +207,17 @@ def snerg_render_backward(handle, grid: snerg_grid, mlp, cams, ray_ids, n_rays, 
                                        int(n_rays), ctypes.byref(opts), _ptr(aux), _ptr(grad_rgba),
                                        _ptr(grad_mlp), _ptr(grad_dens), _ptr(grad_rgb), _ptr(grad_feat),
                                        _stream(stream)), "snerg_render_backward")
+
+
+def snerg_loss_mse(handle, rgba, target, n, grad_rgba, loss, target_ids=None, stream=None):
+    _check(lib().snerg_loss_mse(handle.h, _ptr(rgba), _ptr(target), _ptr(target_ids), int(n), _ptr(grad_rgba),
+                                _ptr(loss), _stream(stream)), "snerg_loss_mse")
+
+
+def snerg_adam_step(handle, param, grad, m, v, n, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    cfg = snerg_adam(float(lr), float(beta1), float(beta2), float(eps), int(step), 0)
+    _check(lib().snerg_adam_step(handle.h, _ptr(param), _ptr(grad), _ptr(m), _ptr(v), int(n), ctypes.byref(cfg),
+                                 _stream(stream)), "snerg_adam_step")
 
 
 def snerg_trace_visits(handle, grid: snerg_grid, cams, ray_ids, n_rays, opts, max_visits, visits, counts,

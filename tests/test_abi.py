@@ -160,3 +160,33 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(S, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="missing"):
         S.lib()
+
+
+def test_finetuning_entry_point_validation():
+    lib = S.lib()
+    loss = lambda n, r=FAKE, t=FAKE, g=FAKE, l=FAKE: lib.snerg_loss_mse(None, r, t, None, n, g, l, None)
+    assert loss(-1) == S.SNERG_ERR_INVALID_ARG
+    assert loss(4, l=None) == S.SNERG_ERR_INVALID_ARG
+    assert loss(4, t=None) == S.SNERG_ERR_INVALID_ARG
+    assert loss(0, r=None, t=None, g=None) == S.SNERG_ERR_INVALID_ARG and "handle" in last_error()
+    adam = lambda cfg, n=8, p=FAKE: lib.snerg_adam_step(None, p, FAKE, FAKE, FAKE, n, ctypes.byref(cfg), None)
+    assert adam(S.snerg_adam(3e-4, 0.9, 0.999, 1e-8, 0, 0)) == S.SNERG_ERR_INVALID_ARG        # step 0
+    assert adam(S.snerg_adam(3e-4, 1.0, 0.999, 1e-8, 1, 0)) == S.SNERG_ERR_INVALID_ARG        # beta1 = 1
+    assert adam(S.snerg_adam(float("nan"), 0.9, 0.999, 1e-8, 1, 0)) == S.SNERG_ERR_INVALID_ARG
+    assert adam(S.snerg_adam(3e-4, 0.9, 0.999, 0.0, 1, 0)) == S.SNERG_ERR_INVALID_ARG         # eps = 0
+    assert adam(S.snerg_adam(3e-4, 0.9, 0.999, 1e-8, 1, 0), p=None) == S.SNERG_ERR_INVALID_ARG
+    assert adam(S.snerg_adam(3e-4, 0.9, 0.999, 1e-8, 1, 0)) == S.SNERG_ERR_INVALID_ARG and "handle" in last_error()
+    assert lib.snerg_adam_step(None, None, None, None, None, 8, None, None) == S.SNERG_ERR_INVALID_ARG
+
+
+def test_mlp_only_backward_accepts_uint8_grids():
+    lib = S.lib()
+    cams = (S.snerg_camera * 1)(good_camera())
+    u8 = S.snerg_grid(64, 8, 8, S.SNERG_U8, FAKE.value, FAKE.value, 50.0, 0)
+    o = S.make_opts(mlp_grad_only=True)
+    rc = lib.snerg_render_backward(None, ctypes.byref(u8), FAKE, cams, 1, None, 32, ctypes.byref(o), FAKE, FAKE,
+                                   FAKE, None, None, None, None)
+    assert rc == S.SNERG_ERR_INVALID_ARG and "handle" in last_error()   # got past every argument check
+    rc = lib.snerg_render_backward(None, ctypes.byref(u8), FAKE, cams, 1, None, 32, ctypes.byref(o), FAKE, FAKE,
+                                   None, None, None, None, None)
+    assert rc == S.SNERG_ERR_INVALID_ARG and "grad_mlp" in last_error()
