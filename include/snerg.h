@@ -91,6 +91,15 @@ extern "C" {
 #define SNERG_FLAG_PERSISTENT (1u << 1) /* one persistent launch over a global tile queue */
 #define SNERG_FLAG_GRAPH (1u << 2)      /* replay the launch from a captured HIP graph */
 #define SNERG_FLAG_MLP_GRAD_ONLY (1u << 3) /* backward: MLP gradient only (any grid dtype) */
+/* Render variants of the paper's own viewer (they change the image):
+ * NN_GATE composites a sample only if the voxel nearest to it (voxel floor(x)
+ * in voxel units) has non-zero density, the in-block test of the WebGL
+ * renderer (Appendix A), instead of the exact "some corner with non-zero
+ * density and weight"; UNPREMULTIPLY scales C_d, V and alpha by
+ * min(1, 1.5 alpha) / alpha after compositing (Eq. 9, forward-facing scenes),
+ * before the deferred MLP; forward only. */
+#define SNERG_FLAG_NN_GATE (1u << 4)
+#define SNERG_FLAG_UNPREMULTIPLY (1u << 5)
 
 #define SNERG_MLP_PARAMS 883 /* W1[16][34] b1[16] W2[16][16] b2[16] W3[3][16] b3[3], [out][in] */
 

@@ -49,7 +49,8 @@ class _Camera(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("bg", ctypes.c_double * 3), ("t_stop", ctypes.c_double),
-                ("early_stop", ctypes.c_int32), ("mlp_on", ctypes.c_int32)]
+                ("early_stop", ctypes.c_int32), ("mlp_on", ctypes.c_int32),
+                ("nn_gate", ctypes.c_int32), ("unpremultiply", ctypes.c_int32)]
 
 
 def _load():
@@ -122,10 +123,12 @@ def _cams(cams):
     return arr
 
 
-def _opts(bg=(1.0, 1.0, 1.0), t_stop=DEFAULT_T_STOP, early_stop=True, mlp_on=True):
+def _opts(bg=(1.0, 1.0, 1.0), t_stop=DEFAULT_T_STOP, early_stop=True, mlp_on=True, nn_gate=False,
+          unpremultiply=False):
     o = _Opts()
     o.bg[:] = [float(v) for v in bg]
     o.t_stop, o.early_stop, o.mlp_on = float(t_stop), int(bool(early_stop)), int(bool(mlp_on))
+    o.nn_gate, o.unpremultiply = int(bool(nn_gate)), int(bool(unpremultiply))
     return o
 
 
@@ -199,7 +202,7 @@ def mlp_eval(mlp, x):
 
 
 def render(og: OracleGrid, mlp, cams, ray_ids=None, bg=(1.0, 1.0, 1.0), t_stop=DEFAULT_T_STOP,
-           early_stop=True, mlp_on=True, threads: int = 0):
+           early_stop=True, mlp_on=True, threads: int = 0, nn_gate=False, unpremultiply=False):
     """Renders the given rays (all rays when ray_ids is None).  Returns a dict
     with rgba [n,4], aux [n,9] (C_d, V, T, gate) and counters [n,5]
     (macroblocks traversed, occupied macroblocks visited, in-block samples,
@@ -207,7 +210,7 @@ def render(og: OracleGrid, mlp, cams, ray_ids=None, bg=(1.0, 1.0, 1.0), t_stop=D
     lib = _load()
     ids, n = _ids(ray_ids, cams)
     c = _cams(cams)
-    o = _opts(bg, t_stop, early_stop, mlp_on)
+    o = _opts(bg, t_stop, early_stop, mlp_on, nn_gate, unpremultiply)
     p = _mlp_vec(mlp)
     rgba = np.zeros((n, 4), np.float64)
     aux = np.zeros((n, 9), np.float64)
@@ -218,12 +221,12 @@ def render(og: OracleGrid, mlp, cams, ray_ids=None, bg=(1.0, 1.0, 1.0), t_stop=D
 
 
 def trace_visits(og: OracleGrid, cams, ray_ids=None, early_stop=False, t_stop=DEFAULT_T_STOP,
-                 max_visits: int = 256, threads: int = 0):
+                 max_visits: int = 256, threads: int = 0, nn_gate=False):
     """Occupied macroblocks visited per ray (linear indirection index), [n, max_visits], and counts [n]."""
     lib = _load()
     ids, n = _ids(ray_ids, cams)
     c = _cams(cams)
-    o = _opts(t_stop=t_stop, early_stop=early_stop, mlp_on=False)
+    o = _opts(t_stop=t_stop, early_stop=early_stop, mlp_on=False, nn_gate=nn_gate)
     vis = np.full((n, max_visits), -1, np.int32)
     cnt = np.zeros(n, np.int32)
     _check(lib.orc_trace_visits(ctypes.byref(og.struct), c, len(cams), _ptr(ids), n, ctypes.byref(o),
@@ -232,7 +235,7 @@ def trace_visits(og: OracleGrid, cams, ray_ids=None, early_stop=False, t_stop=DE
 
 
 def render_grad(og: OracleGrid, mlp, cams, g_rgba, ray_ids=None, bg=(1.0, 1.0, 1.0),
-                t_stop=DEFAULT_T_STOP, early_stop=True, mlp_on=True, g_cv=None):
+                t_stop=DEFAULT_T_STOP, early_stop=True, mlp_on=True, g_cv=None, nn_gate=False):
     """Gradient of sum(g_rgba * rgba) w.r.t. the 883 MLP parameters and the
     grid values (float grids only).  Returns (g_mlp, g_dens, g_rgb, g_feat).
     g_cv [n, 7] (optional) supplies each ray's dL/dC_d, dL/dV in place of the
@@ -241,7 +244,7 @@ def render_grad(og: OracleGrid, mlp, cams, g_rgba, ray_ids=None, bg=(1.0, 1.0, 1
     assert og.dtype != U8, "gradients need a float (shadow) grid"
     ids, n = _ids(ray_ids, cams)
     c = _cams(cams)
-    o = _opts(bg, t_stop, early_stop, mlp_on)
+    o = _opts(bg, t_stop, early_stop, mlp_on, nn_gate)
     p = _mlp_vec(mlp)
     g = np.ascontiguousarray(g_rgba, np.float64).reshape(n, 4)
     gm = np.zeros(N_PARAMS, np.float64)

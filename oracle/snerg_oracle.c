@@ -92,6 +92,8 @@ typedef struct {
     double t_stop;
     int32_t early_stop;
     int32_t mlp_on;
+    int32_t nn_gate;        /* Appendix A: skip a sample whose nearest voxel has zero density */
+    int32_t unpremultiply;  /* Eq. 9: scale colour, features and alpha by min(1, 1.5a)/a */
 } orc_opts;
 
 /* ------------------------------------------------------------------ helpers */
@@ -193,6 +195,15 @@ static int sample_point(const orc_grid *g, const int64_t P[3], double out[8],
     out[0] = g->sigma_scale * acc[0];
     for (int ch = 1; ch < 8; ++ch) out[ch] = acc[ch];
     return active;
+}
+
+/* The WebGL renderer's in-block test (Appendix A): the density of the voxel
+ * whose centre is nearest to P, i.e. voxel floor(P) in voxel units, is
+ * non-zero (empty blocks and the outside read as zero). */
+static int nearest_nonzero(const orc_grid *g, const int64_t P[3])
+{
+    int64_t vi = voxel_index(g, floor_div(P[0], 65536), floor_div(P[1], 65536), floor_div(P[2], 65536));
+    return vi >= 0 && grid_value(g, g->dens, vi) != 0.0;
 }
 
 int orc_sample(const orc_grid *g, const int64_t P[3], double out[8], int32_t *active)
@@ -416,6 +427,7 @@ static int march_ray(const orc_grid *g, const double *mlp, const orc_camera *cam
             prev_vis = blk;
         }
         cnt.inblock_samples++;
+        if (op->nn_gate && !nearest_nonzero(g, P)) continue;
         double smp[8];
         if (!sample_point(g, P, smp, NULL, NULL)) continue;
         cnt.active_samples++;
@@ -427,6 +439,16 @@ static int march_ray(const orc_grid *g, const double *mlp, const orc_camera *cam
         }
     }
     if (n_visits) *n_visits = nv;
+    if (op->unpremultiply) {
+        /* Eq. 9, after compositing and before the deferred network */
+        double alpha = 1.0 - st.T;
+        if (alpha > 0.0) {
+            double sc = (1.5 * alpha < 1.0 ? 1.5 * alpha : 1.0) / alpha;
+            for (int ch = 0; ch < 3; ++ch) st.C[ch] *= sc;
+            for (int ch = 0; ch < 4; ++ch) st.V[ch] *= sc;
+            st.T = 1.0 - alpha * sc;
+        }
+    }
 
     double R[3] = {0.0, 0.0, 0.0};
     if (st.gate && op->mlp_on && mlp) {
@@ -580,6 +602,7 @@ int orc_render_grad(const orc_grid *g, const double *mlp, const orc_camera *cams
 {
     if (check_grid(g) || g->dtype == ORC_U8 || !cams || n_cams <= 0 || !op || !g_rgba) return ORC_EINVAL;
     if (!g_mlp || !g_dens || !g_rgb || !g_feat || (!mlp && op->mlp_on)) return ORC_EINVAL;
+    if (op->unpremultiply) return ORC_EINVAL; /* no gradient through Eq. 9 */
     const double delta = 1.0 / (double)g->N;
     rec_list rec = {NULL, 0, 0};
     for (int64_t i = 0; i < n_rays; ++i) {

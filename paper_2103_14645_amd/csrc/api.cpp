@@ -90,7 +90,8 @@ int check_opts(const snerg_opts* o) {
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(o->bg[a])) return fail(SNERG_ERR_INVALID_ARG, "opts->bg must be finite");
     if (!std::isfinite(o->t_stop) || o->t_stop < 0.0f) return fail(SNERG_ERR_INVALID_ARG, "opts->t_stop must be finite and >= 0");
-    const uint32_t known = SNERG_FLAG_MLP_FP16 | SNERG_FLAG_PERSISTENT | SNERG_FLAG_GRAPH | SNERG_FLAG_MLP_GRAD_ONLY;
+    const uint32_t known = SNERG_FLAG_MLP_FP16 | SNERG_FLAG_PERSISTENT | SNERG_FLAG_GRAPH | SNERG_FLAG_MLP_GRAD_ONLY |
+                           SNERG_FLAG_NN_GATE | SNERG_FLAG_UNPREMULTIPLY;
     if (o->flags & ~known) return fail(SNERG_ERR_UNSUPPORTED, "unknown opts->flags bits");
     return SNERG_OK;
 }
@@ -129,6 +130,8 @@ RenderOpts render_opts(const snerg_opts* o) {
     r.t_stop = o->t_stop;
     r.early_stop = o->early_stop ? 1 : 0;
     r.mlp_on = o->mlp_on ? 1 : 0;
+    r.nn_gate = (o->flags & SNERG_FLAG_NN_GATE) ? 1 : 0;
+    r.unpremultiply = (o->flags & SNERG_FLAG_UNPREMULTIPLY) ? 1 : 0;
     return r;
 }
 
@@ -435,6 +438,8 @@ int snerg_render_backward(snerg_handle* h, const snerg_grid* grid, const float* 
     int rc = common_render_checks(grid, mlp, true, cams, n_cams, ray_ids, n_rays, opts, &total);
     if (rc) return rc;
     const bool mlp_only = (opts->flags & SNERG_FLAG_MLP_GRAD_ONLY) != 0;
+    if (opts->flags & SNERG_FLAG_UNPREMULTIPLY)
+        return fail(SNERG_ERR_UNSUPPORTED, "no backward through SNERG_FLAG_UNPREMULTIPLY");
     if (!mlp_only && grid->dtype != SNERG_F32)
         return fail(SNERG_ERR_UNSUPPORTED, "grid gradients need a SNERG_F32 grid");
     if (!aux || !grad_rgba) return fail(SNERG_ERR_INVALID_ARG, "aux/grad_rgba is NULL");

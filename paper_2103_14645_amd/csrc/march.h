@@ -97,6 +97,19 @@ __device__ __forceinline__ void interp_u8(const Corners8& cn, const int32_t fr[3
     smp.active = sd > 0.0f;
 }
 
+// Index of the corner nearest to the sample (the voxel floor(x) in voxel
+// units): on each axis the upper corner when the fraction is >= 1/2.
+__host__ __device__ __forceinline__ int nearest_corner(const int32_t fr[3]) {
+    return (fr[0] >= 32768 ? 1 : 0) | (fr[1] >= 32768 ? 2 : 0) | (fr[2] >= 32768 ? 4 : 0);
+}
+
+// Density byte of the nearest corner is non-zero (the WebGL renderer's test).
+__device__ __forceinline__ bool nearest_nonzero_u8(const Corners8& cn, const int32_t fr[3]) {
+    const int c = nearest_corner(fr);
+    const u32x4 r = (c & 6) == 0 ? cn.row[0] : ((c & 6) == 2 ? cn.row[1] : ((c & 6) == 4 ? cn.row[2] : cn.row[3]));
+    return (((c & 1) ? r.z : r.x) & 0xFFu) != 0u;
+}
+
 // Gather at padded cell p (each in [0, B]) of a uint8 block.
 __device__ __forceinline__ void gather_u8(const uint8_t* __restrict__ blk, int Bp, const int32_t p[3],
                                           const int32_t fr[3], Sample& smp) {
@@ -106,26 +119,32 @@ __device__ __forceinline__ void gather_u8(const uint8_t* __restrict__ blk, int B
 }
 
 // Gather at padded cell p of a float32 block (32 bytes per voxel).
+// With nn_gate the sample counts as active only when the nearest corner's
+// density is non-zero (the WebGL renderer's test; that corner always has
+// non-zero weight).
 __device__ __forceinline__ void gather_f32(const uint8_t* __restrict__ blk, int Bp, const int32_t p[3],
-                                           const int32_t fr[3], Sample& smp) {
+                                           const int32_t fr[3], Sample& smp, bool nn_gate = false) {
     const float4* base = reinterpret_cast<const float4*>(blk) + (int64_t((p[2] * Bp + p[1]) * Bp + p[0]) << 1);
     const int sy = Bp * 2, sz = Bp * Bp * 2;
     float w[8];
     corner_weights(fr, w);
     float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     bool act = false;
+    const int cnn = nearest_corner(fr);
+    float dnn = 0.f;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
         const float4* q = base + ((c & 4) ? sz : 0) + ((c & 2) ? sy : 0) + ((c & 1) ? 2 : 0);
         const float4 a = q[0], b = q[1];
         act |= (a.x != 0.f) && corner_live(c, fr);
+        dnn = c == cnn ? a.x : dnn;
         acc[0] += w[c] * a.x; acc[1] += w[c] * a.y; acc[2] += w[c] * a.z; acc[3] += w[c] * a.w;
         acc[4] += w[c] * b.x; acc[5] += w[c] * b.y; acc[6] += w[c] * b.z; acc[7] += w[c] * b.w;
     }
     smp.sigma_raw = acc[0];
     smp.rgb[0] = acc[1]; smp.rgb[1] = acc[2]; smp.rgb[2] = acc[3];
     smp.feat[0] = acc[4]; smp.feat[1] = acc[5]; smp.feat[2] = acc[6]; smp.feat[3] = acc[7];
-    smp.active = act;
+    smp.active = nn_gate ? dnn != 0.f : act;
 }
 
 // Occupancy lookup: rank of macroblock `lin` in scan order, or -1 if empty.

@@ -37,6 +37,7 @@ __device__ __forceinline__ void march_composite(const RenderArgs& a, const uint2
     const float kx = g.sigma_scale * cs / float(g.N);
     const float t_stop = a.opts.t_stop;
     const bool early = a.opts.early_stop != 0;
+    const bool nn_gate = a.opts.nn_gate != 0;
     // Consecutive samples often fall in the same cell (the step is half a
     // voxel): its corners are then reused instead of loaded again.
     const uint8_t* cached = nullptr;
@@ -53,8 +54,9 @@ __device__ __forceinline__ void march_composite(const RenderArgs& a, const uint2
                     cached = cell;
                 }
                 interp_u8(cn, fr, smp);
+                if (nn_gate) smp.active = nearest_nonzero_u8(cn, fr);
             } else {
-                gather_f32(vox, g.Bp, p, fr, smp);
+                gather_f32(vox, g.Bp, p, fr, smp, nn_gate);
             }
             if (!smp.active) return false;
             composite(st, smp, kx, cs);
@@ -105,6 +107,18 @@ __device__ __forceinline__ void render_ray(const RenderArgs& a, const uint2* occ
         // compiler carries its FP64 form through the march)
         asm volatile("" : "+v"(d[0]), "+v"(d[1]), "+v"(d[2]));
         march_composite<VT>(a, occ, o, s, st);
+        if (a.opts.unpremultiply) {
+            // Eq. 9: saturate alpha above 2/3, keep soft edges below
+            const float al = 1.0f - st.T;
+            if (al > 0.0f) {
+                const float sc = fminf(1.0f, 1.5f * al) / al;
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) st.C[ch] *= sc;
+#pragma unroll
+                for (int ch = 0; ch < 4; ++ch) st.V[ch] *= sc;
+                st.T = 1.0f - al * sc;
+            }
+        }
     }
     float R[3] = {0.f, 0.f, 0.f};
     const bool use_mlp = valid && st.gate && a.opts.mlp_on;
@@ -204,7 +218,14 @@ __global__ __launch_bounds__(256) void k_trace(RenderArgs a) {
         [&](int32_t n) { n_in += n; },
         [&](int64_t, int32_t, const uint8_t* vox, const int32_t p[3], const int32_t fr[3]) {
             Sample smp;
-            if (VT == 0) gather_u8(vox, g.Bp, p, fr, smp); else gather_f32(vox, g.Bp, p, fr, smp);
+            if (VT == 0) {
+                Corners8 cn;
+                load_corners_u8(vox + (uint64_t(cell_index(p, uint32_t(g.Bp), uint32_t(g.Bp * g.Bp))) << 3), g.Bp, cn);
+                interp_u8(cn, fr, smp);
+                if (a.opts.nn_gate) smp.active = nearest_nonzero_u8(cn, fr);
+            } else {
+                gather_f32(vox, g.Bp, p, fr, smp, a.opts.nn_gate != 0);
+            }
             if (!smp.active) return false;
             ++n_act;
             composite(st, smp, kx, cs);

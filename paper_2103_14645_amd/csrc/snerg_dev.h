@@ -111,6 +111,8 @@ struct RenderOpts {
     float t_stop;
     int32_t early_stop;
     int32_t mlp_on;
+    int32_t nn_gate;        // composite only samples whose nearest voxel has density
+    int32_t unpremultiply;  // Eq. 9 after compositing
 };
 
 // ---------------------------------------------------------------- integers

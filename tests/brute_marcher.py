@@ -46,7 +46,7 @@ def dense_arrays(grid, values=None):
 
 
 def march(grid, lattice, mlp, values=None, bg=(1.0, 1.0, 1.0), t_stop=1e-3, early_stop=True,
-          mlp_on=True, sigma_scale=50.0):
+          mlp_on=True, sigma_scale=50.0, nn_gate=False, unpremultiply=False):
     """lattice: (o [n,3], s [n,3], d [n,3]) per ray.  Returns rgba [n,4], gate [n],
     visits (list of lists of linear macroblock indices) and counts of composited samples."""
     N, B = grid.N, grid.B
@@ -84,6 +84,10 @@ def march(grid, lattice, mlp, values=None, bg=(1.0, 1.0, 1.0), t_stop=1e-3, earl
                 col += w[..., None] * Rn[idx[..., 2], idx[..., 1], idx[..., 0]]
                 fea += w[..., None] * Fn[idx[..., 2], idx[..., 1], idx[..., 0]]
     use = blk_occ & act
+    if nn_gate:
+        # the voxel whose centre is nearest: floor(P) in voxel units
+        nn = np.clip(np.floor_divide(P, 65536), -1, N) + 1
+        use &= Dn[nn[..., 2], nn[..., 1], nn[..., 0]] != 0
     sigma = np.where(use, sigma_scale * sig, 0.0)
     delta = 1.0 / N
     one_minus = np.exp(-sigma * delta)                               # 1 - alpha
@@ -104,6 +108,10 @@ def march(grid, lattice, mlp, values=None, bg=(1.0, 1.0, 1.0), t_stop=1e-3, earl
     V = np.einsum("nk,nkc->nc", w, fea)
     T = T_after[:, -1]
     gate = use.any(axis=1)
+    if unpremultiply:
+        a = 1.0 - T
+        sc = np.where(a > 0, np.minimum(1.0, 1.5 * a) / np.where(a > 0, a, 1.0), 1.0)
+        C, V, T = C * sc[:, None], V * sc[:, None], np.where(a > 0, 1.0 - a * sc, T)
 
     R = np.zeros((n, 3))
     if mlp_on and mlp is not None:

@@ -190,3 +190,18 @@ def test_mlp_only_backward_accepts_uint8_grids():
     rc = lib.snerg_render_backward(None, ctypes.byref(u8), FAKE, cams, 1, None, 32, ctypes.byref(o), FAKE, FAKE,
                                    None, None, None, None, None)
     assert rc == S.SNERG_ERR_INVALID_ARG and "grad_mlp" in last_error()
+
+
+def test_unpremultiply_has_no_backward():
+    lib = S.lib()
+    cams = (S.snerg_camera * 1)(good_camera())
+    f32 = S.snerg_grid(64, 8, 8, S.SNERG_F32, FAKE.value, FAKE.value, 50.0, 0)
+    for kw in (dict(unpremultiply=True), dict(unpremultiply=True, mlp_grad_only=True)):
+        o = S.make_opts(**kw)
+        rc = lib.snerg_render_backward(None, ctypes.byref(f32), FAKE, cams, 1, None, 32, ctypes.byref(o), FAKE, FAKE,
+                                       FAKE, FAKE, FAKE, FAKE, None)
+        assert rc == S.SNERG_ERR_UNSUPPORTED and "UNPREMULTIPLY" in last_error()
+    o = S.make_opts(nn_gate=True)   # the gate has a backward
+    rc = lib.snerg_render_backward(None, ctypes.byref(f32), FAKE, cams, 1, None, 32, ctypes.byref(o), FAKE, FAKE,
+                                   FAKE, FAKE, FAKE, FAKE, None)
+    assert rc == S.SNERG_ERR_INVALID_ARG and "handle" in last_error()

@@ -423,3 +423,74 @@ def test_oracle_ray_ids_select_rays():
     assert np.array_equal(full["rgba"][ids], part["rgba"])
     with pytest.raises(RuntimeError):
         O.render(og, mlp, cams, ray_ids=np.array([93]))
+
+
+# ------------------------------------------------- render variants (flags)
+
+@pytest.mark.parametrize("seed,n_occ,early", [(0, 64, True), (2, 200, False), (5, 120, True)])
+def test_variants_match_brute_force(seed, n_occ, early):
+    # the nearest-voxel gate of the WebGL renderer (Appendix A) and the
+    # partial un-premultiply of Eq. 9, each against the dense marcher
+    g = W.tiny_grid(n_occupied=n_occ, seed=seed)
+    mlp = W.mlp_weights(seed + 10)
+    cam = W.orbit_camera(24, 20, seed=seed + 1)
+    og = O.OracleGrid(g)
+    lat = [O.ray_setup(cam, g.N, i, j) for j in range(cam.H) for i in range(cam.W)]
+    lat = tuple(np.array(a) for a in zip(*lat))
+    for kw in (dict(nn_gate=True), dict(unpremultiply=True), dict(nn_gate=True, unpremultiply=True)):
+        r = O.render(og, mlp, [cam], bg=(0.3, 0.6, 0.9), early_stop=early, **kw)
+        b = brute_marcher.march(g, lat, mlp, bg=(0.3, 0.6, 0.9), early_stop=early, **kw)
+        assert np.max(np.abs(r["rgba"] - b["rgba"])) < 1e-12, kw
+        assert np.array_equal(r["counters"][:, 3], b["n_used"]), kw
+    exact = O.render(og, mlp, [cam], early_stop=False)["counters"][:, 3]
+    gated = O.render(og, mlp, [cam], early_stop=False, nn_gate=True)["counters"][:, 3]
+    assert np.all(gated <= exact) and np.any(gated < exact)   # a strict subset of the samples
+
+
+def _single_voxel_ray(sig_byte, c_bytes):
+    # one voxel (x = 20, y = 29, z = 35) of a 64^3 grid; a ray along +x through
+    # its centre line, samples at voxel units 0, 0.5, 1, ... in x
+    N, B = 64, 8
+    dens = np.zeros((N, N, N), np.uint8)
+    rgb = np.zeros((N, N, N, 3), np.uint8); feat = np.zeros((N, N, N, 4), np.uint8)
+    dens[35, 29, 20] = sig_byte
+    rgb[35, 29, 20] = c_bytes
+    g = W.grid_from_dense(dens, rgb, feat, B, permute_seed=2)
+    y = world_of_voxel_coord(29.5, N); z = world_of_voxel_coord(35.5, N)
+    cam = axis_camera((-2.0, y, z), (1, 0, 0), (0, -1, 0), (0, 0, 1))
+    return O.OracleGrid(g), cam, N
+
+
+def test_nn_gate_single_voxel_closed_form():
+    # Exact predicate: samples at x = 20 (weight 1/2), 20.5 (weight 1) and 21
+    # (weight 1/2) are composited.  Nearest-voxel gate: only x in [20, 21),
+    # i.e. the samples at 20 and 20.5.
+    og, cam, N = _single_voxel_ray(102, (255, 0, 51))
+    sig, dl = 50.0 * 102 / 255, 1.0 / N
+    c = np.array([1.0, 0.0, 0.2])
+    Th, Tf = math.exp(-0.5 * sig * dl), math.exp(-sig * dl)
+    r = O.render(og, None, [cam], mlp_on=False, early_stop=False, bg=(0, 0, 0))
+    assert r["counters"][0, 3] == 3
+    assert r["rgba"][0, 3] == pytest.approx(1 - Th * Tf * Th, rel=1e-13)
+    rn = O.render(og, None, [cam], mlp_on=False, early_stop=False, bg=(0, 0, 0), nn_gate=True)
+    assert rn["counters"][0, 3] == 2
+    assert rn["rgba"][0, 3] == pytest.approx(1 - Th * Tf, rel=1e-13)
+    assert np.allclose(rn["rgba"][0, :3], (1 - Th) * c / 2 + Th * (1 - Tf) * c, rtol=1e-13)
+
+
+def test_unpremultiply_closed_form():
+    # Eq. 9 on a composited alpha a: colour, features and alpha scale by
+    # min(1, 1.5 a) / a, so a >= 2/3 saturates to 1 and the background vanishes.
+    for byte in (40, 255):
+        og, cam, N = _single_voxel_ray(byte, (255, 128, 0))
+        bg = np.array([0.2, 0.4, 0.6])
+        r = O.render(og, None, [cam], mlp_on=False, early_stop=False, bg=bg)
+        u = O.render(og, None, [cam], mlp_on=False, early_stop=False, bg=bg, unpremultiply=True)
+        a = r["rgba"][0, 3]
+        sc = min(1.0, 1.5 * a) / a
+        C = r["aux"][0, :3]
+        assert u["rgba"][0, 3] == pytest.approx(min(1.0, 1.5 * a), rel=1e-14)
+        assert np.allclose(u["rgba"][0, :3], C * sc + (1 - min(1.0, 1.5 * a)) * bg, rtol=1e-13, atol=1e-15)
+    # a ray that composites nothing is left alone
+    e = O.render(og, None, [W.orbit_camera(4, 4, seed=1)], mlp_on=False, unpremultiply=True, bg=bg)
+    assert np.allclose(e["rgba"][e["aux"][:, 8] == 0], np.concatenate([bg, [0.0]]))
