@@ -1,6 +1,6 @@
 """Throughput of the SNeRG render path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs plain,batched,adjoint,large,finetune]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs plain,batched,adjoint,large,finetune,nondeferred]
     python bench.py --legs plain,copy --no-cpu-baseline   # adds the copy-kernel calibration launches
     python bench.py --source-hash                          # hash of the render kernel sources
 
@@ -13,7 +13,8 @@ with its max-abs error against the FP64 oracle, the adjoint (8 views at
 800x800 on a float32 shadow of the 512^3 grid, forward + backward), the
 large case (64 x 1920x1080 in one launch, then 65,536-ray minibatch forward
 + backward), and fine-tuning of the deferred network on the fixed uint8
-grid (render, squared error, MLP backward, Adam per 65,536-ray step).
+grid (render, squared error, MLP backward, Adam per 65,536-ray step), and
+the non-deferred ablation (the network on every sample, FP32 and FP16 MFMA).
 Prints one JSON line on stdout; progress goes to stderr.
 
 roofline.traffic is the measured HBM traffic of one render launch, read from
@@ -295,6 +296,34 @@ def leg_large(args, torch, S, W, O):
     return res
 
 
+def leg_nondeferred(args, torch, S, W, plain):
+    """The performance ablation of Section 6 on the plain 512^3 frame: the
+    view network on every composited sample instead of once per pixel, in
+    FP32 and on FP16 MFMA tiles; the deferral speed-up against the deferred
+    FP32 frame and the per-sample network's FLOP rate."""
+    cfg = W.config("plain512")
+    g, cams, mlp = cfg["grid"], cfg["cams"], cfg["mlp"]
+    h = S.Handle()
+    dg = S.DeviceGrid(h, g.N, g.B, g.indirection, g.dens, g.rgb, g.feat)
+    m = S.mlp_tensor(mlp)
+    n = sum(c.n_rays for c in cams)
+    out = torch.empty((n, 4), device="cuda")
+    carr = S.make_cameras(cams)
+    grid = dg.struct()
+    active = plain["counters"]["active"]
+    res = {}
+    for name, fp16 in (("fp32", False), ("fp16_mfma", True)):
+        opts = S.make_opts(fp16=fp16, per_sample_mlp=True)
+        ms = time_launches(lambda: S.snerg_render(h, grid, m, carr, None, n, opts, out), max(4, args.steps // 2),
+                           2, torch)
+        tflops = active * 2 * (34 * 16 + 16 * 16 + 16 * 3) / (ms * 1e-3) / 1e12
+        res[name] = dict(ms=ms, mrays=n / ms / 1e3, deferral_speedup=ms / plain["ms"], mlp_tflops=tflops,
+                         mlp_frac_fp16_peak=tflops / 2500.0)
+        log(f"non-deferred {name}: {ms:.3f} ms/frame ({n / ms / 1e3:.1f} Mrays/s), deferral speed-up "
+            f"{ms / plain['ms']:.2f}x, per-sample network {tflops:.2f} TFLOP/s")
+    return res
+
+
 def leg_finetune(args, torch, S, W):
     """Fine-tuning of the deferred network on the fixed 512^3 uint8 SNeRG
     (Section 5.5): 65,536-ray minibatches over the 8 adjoint views, targets
@@ -370,7 +399,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--legs", default="plain,batched,adjoint,large,finetune")
+    ap.add_argument("--legs", default="plain,batched,adjoint,large,finetune,nondeferred")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--source-hash", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
@@ -400,6 +429,8 @@ def main():
         extra["large_1024"] = leg_large(args, torch, S, W, O)
     if "finetune" in legs:
         extra["finetune"] = leg_finetune(args, torch, S, W)
+    if "nondeferred" in legs:
+        extra["nondeferred"] = leg_nondeferred(args, torch, S, W, plain)
     if "copy" in legs:
         extra["copy"] = leg_copy(torch)
 
@@ -451,6 +482,9 @@ def main():
                                   "tuning": b["tuning"], "minibatch": b["mb"],
                                   "ms_minibatch_fwd_bwd": round(b["ms_train_step"], 4),
                                   "bwd_mrays": round(b["bwd_mrays"], 3), "cpu_oracle_mrays": round(b["cpu_mrays"], 4)}
+    if "nondeferred" in extra:
+        legs_out["nondeferred_512"] = {k: {kk: round(vv, 5) for kk, vv in v.items()}
+                                       for k, v in extra["nondeferred"].items()}
     if "finetune" in extra:
         f = extra["finetune"]
         legs_out["finetune_mlp_512"] = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in f.items()}

@@ -100,6 +100,12 @@ extern "C" {
  * before the deferred MLP; forward only. */
 #define SNERG_FLAG_NN_GATE (1u << 4)
 #define SNERG_FLAG_UNPREMULTIPLY (1u << 5)
+/* Not deferred (the performance ablation of Section 6): the view network
+ * runs on every composited sample, on that sample's colour and features and
+ * the ray direction, its residual added to the sample's colour before
+ * compositing; nothing runs per pixel.  Forward only, without aux; with
+ * SNERG_FLAG_MLP_FP16 the per-sample network runs on FP16 MFMA tiles. */
+#define SNERG_FLAG_PER_SAMPLE_MLP (1u << 6)
 
 #define SNERG_MLP_PARAMS 883 /* W1[16][34] b1[16] W2[16][16] b2[16] W3[3][16] b3[3], [out][in] */
 

@@ -50,7 +50,7 @@ class _Camera(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("bg", ctypes.c_double * 3), ("t_stop", ctypes.c_double),
                 ("early_stop", ctypes.c_int32), ("mlp_on", ctypes.c_int32),
-                ("nn_gate", ctypes.c_int32), ("unpremultiply", ctypes.c_int32)]
+                ("nn_gate", ctypes.c_int32), ("unpremultiply", ctypes.c_int32), ("per_sample_mlp", ctypes.c_int32)]
 
 
 def _load():
@@ -124,11 +124,12 @@ def _cams(cams):
 
 
 def _opts(bg=(1.0, 1.0, 1.0), t_stop=DEFAULT_T_STOP, early_stop=True, mlp_on=True, nn_gate=False,
-          unpremultiply=False):
+          unpremultiply=False, per_sample_mlp=False):
     o = _Opts()
     o.bg[:] = [float(v) for v in bg]
     o.t_stop, o.early_stop, o.mlp_on = float(t_stop), int(bool(early_stop)), int(bool(mlp_on))
     o.nn_gate, o.unpremultiply = int(bool(nn_gate)), int(bool(unpremultiply))
+    o.per_sample_mlp = int(bool(per_sample_mlp))
     return o
 
 
@@ -202,7 +203,8 @@ def mlp_eval(mlp, x):
 
 
 def render(og: OracleGrid, mlp, cams, ray_ids=None, bg=(1.0, 1.0, 1.0), t_stop=DEFAULT_T_STOP,
-           early_stop=True, mlp_on=True, threads: int = 0, nn_gate=False, unpremultiply=False):
+           early_stop=True, mlp_on=True, threads: int = 0, nn_gate=False, unpremultiply=False,
+           per_sample_mlp=False):
     """Renders the given rays (all rays when ray_ids is None).  Returns a dict
     with rgba [n,4], aux [n,9] (C_d, V, T, gate) and counters [n,5]
     (macroblocks traversed, occupied macroblocks visited, in-block samples,
@@ -210,7 +212,7 @@ def render(og: OracleGrid, mlp, cams, ray_ids=None, bg=(1.0, 1.0, 1.0), t_stop=D
     lib = _load()
     ids, n = _ids(ray_ids, cams)
     c = _cams(cams)
-    o = _opts(bg, t_stop, early_stop, mlp_on, nn_gate, unpremultiply)
+    o = _opts(bg, t_stop, early_stop, mlp_on, nn_gate, unpremultiply, per_sample_mlp)
     p = _mlp_vec(mlp)
     rgba = np.zeros((n, 4), np.float64)
     aux = np.zeros((n, 9), np.float64)

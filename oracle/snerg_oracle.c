@@ -94,6 +94,7 @@ typedef struct {
     int32_t mlp_on;
     int32_t nn_gate;        /* Appendix A: skip a sample whose nearest voxel has zero density */
     int32_t unpremultiply;  /* Eq. 9: scale colour, features and alpha by min(1, 1.5a)/a */
+    int32_t per_sample_mlp; /* not deferred: the view MLP's residual added to every composited sample */
 } orc_opts;
 
 /* ------------------------------------------------------------------ helpers */
@@ -431,6 +432,15 @@ static int march_ray(const orc_grid *g, const double *mlp, const orc_camera *cam
         double smp[8];
         if (!sample_point(g, P, smp, NULL, NULL)) continue;
         cnt.active_samples++;
+        if (op->per_sample_mlp && op->mlp_on && mlp) {
+            /* the network of Eq. 7 on this sample's own colour and features
+             * (as NeRF queries its MLP at every sample), its residual added
+             * to the sample's colour before compositing */
+            double x[MLP_IN], Rk[3];
+            orc_encode(&smp[1], &smp[4], d, x);
+            orc_mlp(mlp, x, Rk);
+            for (int ch = 0; ch < 3; ++ch) smp[1 + ch] += Rk[ch];
+        }
         if (rec && rec_push(rec, P, smp, st.T)) return ORC_ENOMEM;
         comp_step(&st, smp, delta);
         if (op->early_stop && st.T < op->t_stop) {
@@ -451,7 +461,7 @@ static int march_ray(const orc_grid *g, const double *mlp, const orc_camera *cam
     }
 
     double R[3] = {0.0, 0.0, 0.0};
-    if (st.gate && op->mlp_on && mlp) {
+    if (st.gate && op->mlp_on && mlp && !op->per_sample_mlp) {
         double x[MLP_IN];
         orc_encode(st.C, st.V, d, x);
         orc_mlp(mlp, x, R);
@@ -602,7 +612,7 @@ int orc_render_grad(const orc_grid *g, const double *mlp, const orc_camera *cams
 {
     if (check_grid(g) || g->dtype == ORC_U8 || !cams || n_cams <= 0 || !op || !g_rgba) return ORC_EINVAL;
     if (!g_mlp || !g_dens || !g_rgb || !g_feat || (!mlp && op->mlp_on)) return ORC_EINVAL;
-    if (op->unpremultiply) return ORC_EINVAL; /* no gradient through Eq. 9 */
+    if (op->unpremultiply || op->per_sample_mlp) return ORC_EINVAL; /* forward-only variants */
     const double delta = 1.0 / (double)g->N;
     rec_list rec = {NULL, 0, 0};
     for (int64_t i = 0; i < n_rays; ++i) {

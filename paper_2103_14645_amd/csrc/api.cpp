@@ -91,7 +91,7 @@ int check_opts(const snerg_opts* o) {
         if (!std::isfinite(o->bg[a])) return fail(SNERG_ERR_INVALID_ARG, "opts->bg must be finite");
     if (!std::isfinite(o->t_stop) || o->t_stop < 0.0f) return fail(SNERG_ERR_INVALID_ARG, "opts->t_stop must be finite and >= 0");
     const uint32_t known = SNERG_FLAG_MLP_FP16 | SNERG_FLAG_PERSISTENT | SNERG_FLAG_GRAPH | SNERG_FLAG_MLP_GRAD_ONLY |
-                           SNERG_FLAG_NN_GATE | SNERG_FLAG_UNPREMULTIPLY;
+                           SNERG_FLAG_NN_GATE | SNERG_FLAG_UNPREMULTIPLY | SNERG_FLAG_PER_SAMPLE_MLP;
     if (o->flags & ~known) return fail(SNERG_ERR_UNSUPPORTED, "unknown opts->flags bits");
     return SNERG_OK;
 }
@@ -132,6 +132,7 @@ RenderOpts render_opts(const snerg_opts* o) {
     r.mlp_on = o->mlp_on ? 1 : 0;
     r.nn_gate = (o->flags & SNERG_FLAG_NN_GATE) ? 1 : 0;
     r.unpremultiply = (o->flags & SNERG_FLAG_UNPREMULTIPLY) ? 1 : 0;
+    r.per_sample_mlp = (o->flags & SNERG_FLAG_PER_SAMPLE_MLP) ? 1 : 0;
     return r;
 }
 
@@ -391,6 +392,8 @@ int snerg_render(snerg_handle* h, const snerg_grid* grid, const float* mlp, cons
     int rc = common_render_checks(grid, mlp, true, cams, n_cams, ray_ids, n_rays, opts, &total);
     if (rc) return rc;
     if (!out_rgba) return fail(SNERG_ERR_INVALID_ARG, "out_rgba is NULL");
+    if (aux && (opts->flags & SNERG_FLAG_PER_SAMPLE_MLP))
+        return fail(SNERG_ERR_UNSUPPORTED, "aux is not produced with SNERG_FLAG_PER_SAMPLE_MLP");
     if (!h) return fail(SNERG_ERR_INVALID_ARG, "handle is NULL");
     if (n_rays == 0) return SNERG_OK;
     return render_impl(h, grid, mlp, cams, n_cams, ray_ids, n_rays, opts, out_rgba, aux,
@@ -440,6 +443,8 @@ int snerg_render_backward(snerg_handle* h, const snerg_grid* grid, const float* 
     const bool mlp_only = (opts->flags & SNERG_FLAG_MLP_GRAD_ONLY) != 0;
     if (opts->flags & SNERG_FLAG_UNPREMULTIPLY)
         return fail(SNERG_ERR_UNSUPPORTED, "no backward through SNERG_FLAG_UNPREMULTIPLY");
+    if (opts->flags & SNERG_FLAG_PER_SAMPLE_MLP)
+        return fail(SNERG_ERR_UNSUPPORTED, "no backward through SNERG_FLAG_PER_SAMPLE_MLP");
     if (!mlp_only && grid->dtype != SNERG_F32)
         return fail(SNERG_ERR_UNSUPPORTED, "grid gradients need a SNERG_F32 grid");
     if (!aux || !grad_rgba) return fail(SNERG_ERR_INVALID_ARG, "aux/grad_rgba is NULL");

@@ -634,6 +634,7 @@ __global__ __launch_bounds__(64 * kAggWaves) void k_march_backward(BackwardArgs 
                     in_table = 0;
                 }
             }
+            return false;
         });
     if (win.rank >= 0) {
 #pragma unroll

@@ -271,7 +271,8 @@ __host__ __device__ __forceinline__ int64_t march_ray(const GridArgs& g, const u
 // after each inner trip all 64 lanes call on_sync() together, which may
 // therefore use wavefront-wide operations.  `live` false marks a lane
 // without a ray.  on_sample as for march_ray; returning true ends the
-// lane's march.
+// lane's march, and so does on_sync() returning true (after the samples
+// handed over so far).
 template <typename OnSample, typename OnSync>
 __device__ __forceinline__ void march_ray_sync(const GridArgs& g, const uint2* occ, bool live, const int64_t o[3],
                                                const int32_t s[3], OnSample&& on_sample, OnSync&& on_sync) {
@@ -343,7 +344,10 @@ __device__ __forceinline__ void march_ray_sync(const GridArgs& g, const uint2* o
 #pragma unroll
                 for (int a = 0; a < 3; ++a) q[a] += adv * s[a];
             }
-            on_sync();
+            if (on_sync()) {
+                live = false;
+                left = 0;
+            }
         }
         if (live) {
             const int32_t adv = kn - k;

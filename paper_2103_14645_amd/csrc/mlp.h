@@ -108,17 +108,11 @@ __device__ __forceinline__ half4_t relu_to_half(float4_t v) {
     return h;
 }
 
-// All 64 lanes of the wavefront must call this together.  Lanes with
-// use == false get R = 0 (their inputs still flow through the tiles).
-__device__ __forceinline__ void mlp_forward_f16_wave(cfloat* W, bool use, const float C[3],
-                                                     const float V[4], const float d[3], float R[3]) {
-    __shared__ _Float16 xs[kMaxWavesF16][64][kXRow];
+// The network on FP16 MFMA tiles for the inputs staged in xs ([64][kXRow]
+// halves, one row per lane: x padded with zeros to kXPad).  All 64 lanes of
+// the wavefront call this together; lanes with use == false get R = 0.
+__device__ __forceinline__ void mlp_eval_f16_wave(cfloat* W, _Float16 (*xs)[kXRow], bool use, float R[3]) {
     const int lane = threadIdx.x & 63;
-    const int wave = (threadIdx.x >> 6) & (kMaxWavesF16 - 1);
-    float x[kMlpIn];
-    encode_x(C, V, d, x);
-#pragma unroll
-    for (int i = 0; i < kXPad; ++i) xs[wave][lane][i] = _Float16(i < kMlpIn ? x[i] : 0.0f);
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -136,7 +130,7 @@ __device__ __forceinline__ void mlp_forward_f16_wave(cfloat* W, bool use, const 
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         // B operand of layer 1: lane l holds x_{16g + l%16}[16kc + 4(l/16) + v]
-        const _Float16* row = &xs[wave][16 * g + (lane & 15)][4 * (lane >> 4)];
+        const _Float16* row = &xs[16 * g + (lane & 15)][4 * (lane >> 4)];
         float4_t acc = bb1;
 #pragma unroll
         for (int kc = 0; kc < 3; ++kc) {
@@ -157,6 +151,20 @@ __device__ __forceinline__ void mlp_forward_f16_wave(cfloat* W, bool use, const 
         R[i] = use ? sigmoid_f32(z) : 0.0f;
     }
     __builtin_amdgcn_wave_barrier();  // xs is rewritten by the next call
+}
+
+// All 64 lanes of the wavefront must call this together.  Lanes with
+// use == false get R = 0 (their inputs still flow through the tiles).
+__device__ __forceinline__ void mlp_forward_f16_wave(cfloat* W, bool use, const float C[3],
+                                                     const float V[4], const float d[3], float R[3]) {
+    __shared__ _Float16 xs[kMaxWavesF16][64][kXRow];
+    const int lane = threadIdx.x & 63;
+    const int wave = (threadIdx.x >> 6) & (kMaxWavesF16 - 1);
+    float x[kMlpIn];
+    encode_x(C, V, d, x);
+#pragma unroll
+    for (int i = 0; i < kXPad; ++i) xs[wave][lane][i] = _Float16(i < kMlpIn ? x[i] : 0.0f);
+    mlp_eval_f16_wave(W, xs[wave], use, R);
 }
 
 }  // namespace snerg

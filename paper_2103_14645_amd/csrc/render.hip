@@ -260,6 +260,7 @@ static hipError_t launch_render_t(const RenderArgs& a, int wpg, int n_groups, hi
 
 hipError_t launch_render(const RenderArgs& a, int vt, int mlp_mode, int wpg, int n_groups,
                          hipStream_t s) {
+    if (a.opts.per_sample_mlp) return launch_render_ps(a, vt, mlp_mode == kMlpF16, wpg, n_groups, s);
     if (vt == 0) {
         if (mlp_mode == kMlpF16) return launch_render_t<0, kMlpF16>(a, wpg, n_groups, s);
         if (mlp_mode == kMlpF32) return launch_render_t<0, kMlpF32>(a, wpg, n_groups, s);

@@ -113,6 +113,7 @@ struct RenderOpts {
     int32_t mlp_on;
     int32_t nn_gate;        // composite only samples whose nearest voxel has density
     int32_t unpremultiply;  // Eq. 9 after compositing
+    int32_t per_sample_mlp; // not deferred: the network on every composited sample
 };
 
 // ---------------------------------------------------------------- integers

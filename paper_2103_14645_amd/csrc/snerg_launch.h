@@ -71,6 +71,7 @@ hipError_t launch_render(const RenderArgs& a, int vt, int mlp_mode, int waves_pe
 hipError_t launch_trace(const RenderArgs& a, int vt, hipStream_t s);
 hipError_t launch_backward(const BackwardArgs& a, int n_groups, hipStream_t s);
 int backward_partial_rows(int n_groups);
+hipError_t launch_render_ps(const RenderArgs& a, int vt, bool f16, int wpg, int n_groups, hipStream_t s);
 hipError_t launch_mse(const float* rgba, const float* target, const int64_t* ids, int64_t n, float* grad, float* loss,
                       hipStream_t s);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,

@@ -45,8 +45,21 @@ def dense_arrays(grid, values=None):
     return D, R, F, occ
 
 
+def _mlp(mlp, C, V, dirs):
+    """The 34-16-16-3 network on rows of (C, V, d) with d's sin/cos encoding."""
+    W1, b1, W2, b2, W3, b3 = (np.asarray(p, np.float64) for p in mlp.params())
+    pe = []
+    for l in range(4):
+        a = (2.0 ** l) * np.pi * dirs
+        pe += [np.sin(a), np.cos(a)]
+    x = np.concatenate([C, V, dirs] + pe, axis=1)
+    h1 = np.maximum(x @ W1.T + b1, 0.0)
+    h2 = np.maximum(h1 @ W2.T + b2, 0.0)
+    return 1.0 / (1.0 + np.exp(-(h2 @ W3.T + b3)))
+
+
 def march(grid, lattice, mlp, values=None, bg=(1.0, 1.0, 1.0), t_stop=1e-3, early_stop=True,
-          mlp_on=True, sigma_scale=50.0, nn_gate=False, unpremultiply=False):
+          mlp_on=True, sigma_scale=50.0, nn_gate=False, unpremultiply=False, per_sample_mlp=False):
     """lattice: (o [n,3], s [n,3], d [n,3]) per ray.  Returns rgba [n,4], gate [n],
     visits (list of lists of linear macroblock indices) and counts of composited samples."""
     N, B = grid.N, grid.B
@@ -103,6 +116,11 @@ def march(grid, lattice, mlp, values=None, bg=(1.0, 1.0, 1.0), t_stop=1e-3, earl
     else:
         first = np.full(n, kmax + 1)
     T_before = np.concatenate([np.ones((n, 1)), T_after[:, :-1]], axis=1)
+    if per_sample_mlp and mlp_on and mlp is not None:
+        # every sample's colour plus the network's residual on (c_k, v_k, d)
+        K = P.shape[1]
+        dk = np.repeat(dirs[:, None, :], K, axis=1)
+        col = col + _mlp(mlp, col.reshape(-1, 3), fea.reshape(-1, 4), dk.reshape(-1, 3)).reshape(n, K, 3)
     w = np.where(use, T_before * (1.0 - one_minus), 0.0)
     C = np.einsum("nk,nkc->nc", w, col)
     V = np.einsum("nk,nkc->nc", w, fea)
@@ -114,17 +132,8 @@ def march(grid, lattice, mlp, values=None, bg=(1.0, 1.0, 1.0), t_stop=1e-3, earl
         C, V, T = C * sc[:, None], V * sc[:, None], np.where(a > 0, 1.0 - a * sc, T)
 
     R = np.zeros((n, 3))
-    if mlp_on and mlp is not None:
-        W1, b1, W2, b2, W3, b3 = (np.asarray(p, np.float64) for p in mlp.params())
-        pe = []
-        for l in range(4):
-            a = (2.0 ** l) * np.pi * dirs
-            pe += [np.sin(a), np.cos(a)]
-        x = np.concatenate([C, V, dirs] + pe, axis=1)
-        h1 = np.maximum(x @ W1.T + b1, 0.0)
-        h2 = np.maximum(h1 @ W2.T + b2, 0.0)
-        R = 1.0 / (1.0 + np.exp(-(h2 @ W3.T + b3)))
-        R = np.where(gate[:, None], R, 0.0)
+    if mlp_on and mlp is not None and not per_sample_mlp:
+        R = np.where(gate[:, None], _mlp(mlp, C, V, dirs), 0.0)
     rgb = C + T[:, None] * np.asarray(bg)[None, :] + R
     rgba = np.concatenate([rgb, (1.0 - T)[:, None]], axis=1)
 

@@ -205,3 +205,18 @@ def test_unpremultiply_has_no_backward():
     rc = lib.snerg_render_backward(None, ctypes.byref(f32), FAKE, cams, 1, None, 32, ctypes.byref(o), FAKE, FAKE,
                                    FAKE, FAKE, FAKE, FAKE, None)
     assert rc == S.SNERG_ERR_INVALID_ARG and "handle" in last_error()
+
+
+def test_per_sample_mlp_is_forward_only_without_aux():
+    o = S.make_opts(per_sample_mlp=True)
+    assert call_render(opts=o) == S.SNERG_ERR_INVALID_ARG and "handle" in last_error()
+    assert call_render(opts=o, out=FAKE) == S.SNERG_ERR_INVALID_ARG
+    lib = S.lib()
+    grid = S.snerg_grid(64, 8, 8, S.SNERG_U8, FAKE.value, FAKE.value, 50.0, 0)
+    cams = (S.snerg_camera * 1)(good_camera())
+    rc = lib.snerg_render(None, ctypes.byref(grid), FAKE, cams, 1, None, 32, ctypes.byref(o), FAKE, FAKE, None)
+    assert rc == S.SNERG_ERR_UNSUPPORTED and "aux" in last_error()
+    f32 = S.snerg_grid(64, 8, 8, S.SNERG_F32, FAKE.value, FAKE.value, 50.0, 0)
+    rc = lib.snerg_render_backward(None, ctypes.byref(f32), FAKE, cams, 1, None, 32, ctypes.byref(o), FAKE, FAKE,
+                                   FAKE, FAKE, FAKE, FAKE, None)
+    assert rc == S.SNERG_ERR_UNSUPPORTED and "PER_SAMPLE" in last_error()

@@ -101,3 +101,42 @@ def test_variants_on_plain512_sampled_rays():
     err, flagged = parity_error(frame[ids], _oracle(O.OracleGrid(g), mlp, cams, ids=ids, **kw))
     say(f"  max_err={err.max():.3e} near_threshold={flagged}")
     assert err.max() <= 1e-4
+
+
+@pytest.mark.parametrize("fp16", [False, True])
+@pytest.mark.parametrize("n_occ,seed,gate", [(64, 1, False), (200, 2, False), (200, 3, True)])
+def test_per_sample_mlp_matches_oracle(fp16, n_occ, seed, gate):
+    say(f"per-sample mlp fp16={fp16} n_occ={n_occ} seed={seed} gate={gate}")
+    g, cams, mlp = _case(n_occ, seed)
+    dg = device_grid(g)
+    n = sum(c.n_rays for c in cams)
+    opts = S.make_opts(fp16=fp16, per_sample_mlp=True, nn_gate=gate)
+    out = torch.empty((n, 4), device="cuda")
+    S.snerg_render(handle(), dg.struct(), S.mlp_tensor(mlp), S.make_cameras(cams), None, n, opts, out)
+    torch.cuda.synchronize()
+    err, flagged = parity_error(out.cpu().numpy(), _oracle(O.OracleGrid(g), mlp, cams, per_sample_mlp=True, nn_gate=gate))
+    say(f"  max_err={err.max():.3e} near_threshold={flagged}")
+    assert err.max() <= (2e-3 if fp16 else 1e-4)
+
+
+def test_per_sample_mlp_launch_modes_agree_bitwise():
+    g, cams, mlp = _case(200, 2)
+    dg = device_grid(g)
+    for fp16 in (False, True):
+        base = gpu_render(dg, mlp, cams, fp16=fp16, per_sample_mlp=True)
+        for kw in (dict(persistent=True), dict(persistent=True, graph=True)):
+            say(f"per-sample fp16={fp16} {kw}")
+            assert np.array_equal(gpu_render(dg, mlp, cams, fp16=fp16, per_sample_mlp=True, **kw), base)
+        ids = np.random.default_rng(0).permutation(base.shape[0])[:1000]
+        assert np.array_equal(gpu_render(dg, mlp, cams, ids=ids, fp16=fp16, per_sample_mlp=True), base[ids])
+
+
+def test_per_sample_mlp_on_plain512_sampled_rays():
+    say("plain512, per-sample FP16 network: 4000 sampled rays")
+    cfg = W.config("plain512")
+    g, cams, mlp = cfg["grid"], cfg["cams"], cfg["mlp"]
+    frame = gpu_render(device_grid(g), mlp, cams, fp16=True, per_sample_mlp=True)
+    ids = np.sort(np.random.default_rng(9).choice(frame.shape[0], 4000, replace=False))
+    err, flagged = parity_error(frame[ids], _oracle(O.OracleGrid(g), mlp, cams, ids=ids, per_sample_mlp=True))
+    say(f"  max_err={err.max():.3e} near_threshold={flagged}")
+    assert err.max() <= 2e-3

@@ -494,3 +494,34 @@ def test_unpremultiply_closed_form():
     # a ray that composites nothing is left alone
     e = O.render(og, None, [W.orbit_camera(4, 4, seed=1)], mlp_on=False, unpremultiply=True, bg=bg)
     assert np.allclose(e["rgba"][e["aux"][:, 8] == 0], np.concatenate([bg, [0.0]]))
+
+
+def test_per_sample_mlp_zero_network_closed_form():
+    # A zero network outputs sigmoid(0) = 1/2 at every sample, so the
+    # non-deferred render adds (1/2) sum_k w_k = (1 - T)/2 to the deferred
+    # render's diffuse colour, and runs no per-pixel network.
+    g = W.tiny_grid(n_occupied=64, seed=1)
+    cam = W.orbit_camera(16, 12, seed=2)
+    og = O.OracleGrid(g)
+    bg = np.array([0.1, 0.2, 0.3])
+    zero = np.zeros(883)
+    d = O.render(og, zero, [cam], bg=bg, mlp_on=False)
+    p = O.render(og, zero, [cam], bg=bg, per_sample_mlp=True)
+    T = 1.0 - d["rgba"][:, 3]
+    np.testing.assert_allclose(p["rgba"][:, :3], d["rgba"][:, :3] + 0.5 * (1.0 - T)[:, None], rtol=1e-13, atol=1e-15)
+    np.testing.assert_array_equal(p["counters"], d["counters"])
+
+
+@pytest.mark.parametrize("seed,early,gate", [(0, True, False), (2, False, False), (3, True, True)])
+def test_per_sample_mlp_matches_brute_force(seed, early, gate):
+    g = W.tiny_grid(n_occupied=120, seed=seed)
+    mlp = W.mlp_weights(seed + 20)
+    cam = W.orbit_camera(20, 16, seed=seed + 3)
+    og = O.OracleGrid(g)
+    lat = [O.ray_setup(cam, g.N, i, j) for j in range(cam.H) for i in range(cam.W)]
+    lat = tuple(np.array(a) for a in zip(*lat))
+    r = O.render(og, mlp, [cam], bg=(0.3, 0.6, 0.9), early_stop=early, per_sample_mlp=True, nn_gate=gate)
+    b = brute_marcher.march(g, lat, mlp, bg=(0.3, 0.6, 0.9), early_stop=early, per_sample_mlp=True, nn_gate=gate)
+    assert np.max(np.abs(r["rgba"] - b["rgba"])) < 1e-12
+    deferred = O.render(og, mlp, [cam], bg=(0.3, 0.6, 0.9), early_stop=early, nn_gate=gate)["rgba"]
+    assert np.max(np.abs(r["rgba"] - deferred)) > 1e-3   # a different image, same samples
