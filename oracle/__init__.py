@@ -71,8 +71,9 @@ def _load():
         lib.orc_trace_visits.argtypes = [P, P, ctypes.c_int32, P, ctypes.c_int64, P, ctypes.c_int32,
                                          P, P, ctypes.c_int32]
         lib.orc_render_grad.argtypes = [P, P, P, ctypes.c_int32, P, ctypes.c_int64, P, P, P, P, P, P, P]
+        lib.orc_bake_visibility.argtypes = [ctypes.c_int32, P, P, ctypes.c_int32, P, P, ctypes.c_int32]
         for f in (lib.orc_ray_setup, lib.orc_sample, lib.orc_composite, lib.orc_encode, lib.orc_mlp,
-                  lib.orc_render, lib.orc_trace_visits, lib.orc_render_grad):
+                  lib.orc_render, lib.orc_trace_visits, lib.orc_render_grad, lib.orc_bake_visibility):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib

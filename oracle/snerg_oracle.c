@@ -715,3 +715,85 @@ int orc_render_grad(const orc_grid *g, const double *mlp, const orc_camera *cams
 }
 
 int orc_mlp_nparams(void) { return MLP_NPARAM; }
+
+/* ------------------------------------------------------------- baking */
+
+/*
+ * Voxel visibility from training views (Section 5.3): the largest
+ * transmittance between each voxel and any training camera.  sigma is a
+ * densely evaluated field, float64 [N^3] (x fastest), density per unit
+ * length of the world box.  Every ray of every camera is marched over the
+ * whole sample lattice of step 1 (no early stop, no skipping); sample k lies
+ * in voxel floor(P_k / 2^16), reads that voxel's density, and sees
+ *     T_k = exp(-delta * sum_{j < k} sigma_j),  delta = 1/N,
+ * the sum running over the ray's earlier samples inside the grid.
+ * vis [N^3] receives max over all samples in the voxel of T_k (0 when no
+ * sample falls in it); depth [N^3] (nullable) the smallest prefix sum
+ * sum_{j<k} sigma_j of those samples (+inf when none), whose exponent gives
+ * vis.  Rays are split over threads; each thread keeps its own copy of
+ * the outputs, merged at the end.
+ */
+int orc_bake_visibility(int32_t N, const double *sigma, const orc_camera *cams, int32_t n_cams, double *vis,
+                        double *depth, int32_t n_threads)
+{
+    if (N <= 0 || !sigma || !cams || n_cams <= 0 || !vis) return ORC_EINVAL;
+    const int64_t nv = (int64_t)N * N * N;
+    const int64_t L = (int64_t)N * 65536;
+    const double delta = 1.0 / (double)N;
+    int64_t total = 0;
+    for (int32_t c = 0; c < n_cams; ++c) total += (int64_t)cams[c].W * cams[c].H;
+    const int nt = set_threads(n_threads);
+    double *buf = (double *)malloc(sizeof(double) * (size_t)nv * (size_t)nt);
+    if (!buf) return ORC_ENOMEM;
+    for (int64_t i = 0; i < nv * nt; ++i) buf[i] = INFINITY;
+#pragma omp parallel
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *mine = buf + (size_t)nv * (size_t)tid;
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t r = 0; r < total; ++r) {
+            int32_t ci;
+            int64_t px, py;
+            locate_ray(cams, n_cams, r, &ci, &px, &py);
+            int64_t o[3], s[3];
+            double d[3];
+            orc_ray_setup(&cams[ci], N, px, py, o, s, d);
+            int64_t smax = 0, omax = 0;
+            for (int a = 0; a < 3; ++a) {
+                if (llabs(s[a]) > smax) smax = llabs(s[a]);
+                if (llabs(o[a]) > omax) omax = llabs(o[a]);
+            }
+            const int64_t k_limit = (smax > 0) ? (omax + L) / smax + 2 : 0;
+            double sum = 0.0;
+            int seen_inside = 0;
+            for (int64_t k = 0; k <= k_limit; ++k) {
+                int64_t P[3];
+                int inside = 1;
+                for (int a = 0; a < 3; ++a) {
+                    P[a] = o[a] + k * s[a];
+                    if (P[a] < 0 || P[a] >= L) inside = 0;
+                }
+                if (!inside) {
+                    if (seen_inside) break;
+                    continue;
+                }
+                seen_inside = 1;
+                const int64_t v = ((P[2] >> 16) * N + (P[1] >> 16)) * N + (P[0] >> 16);
+                if (sum < mine[v]) mine[v] = sum;
+                sum = sum + sigma[v];
+            }
+        }
+    }
+    for (int64_t v = 0; v < nv; ++v) {
+        double m = INFINITY;
+        for (int t = 0; t < nt; ++t)
+            if (buf[(size_t)nv * t + v] < m) m = buf[(size_t)nv * t + v];
+        vis[v] = isinf(m) ? 0.0 : exp(-delta * m);
+        if (depth) depth[v] = m;
+    }
+    free(buf);
+    return ORC_OK;
+}

@@ -61,6 +61,11 @@ def _shellgen():
                                       ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
                                       ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int32,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        lib.shellgen_dense.restype = ctypes.c_int
+        lib.shellgen_dense.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_int32, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p]
         _lib = lib
     return _lib
 
@@ -168,6 +173,40 @@ def shell_grid(N: int, B: int, amplitude: float, seed: int = SEED_GRID, r0: floa
     return Grid(N, B, ind, dens, rgb, feat,
                 meta=dict(kind="shell", seed=seed, amplitude=amplitude, r0=r0, base_freq=base_freq,
                           occupancy=float(n) / G ** 3))
+
+
+@dataclasses.dataclass
+class DenseField:
+    """A densely evaluated radiance field (what Section 5.3 bakes from):
+    sigma float32 [N, N, N] ([z, y, x]; density per unit length of the world
+    box), rgb float32 [N, N, N, 3] and feat float32 [N, N, N, 4] in [0, 1]."""
+    N: int
+    sigma: np.ndarray
+    rgb: np.ndarray
+    feat: np.ndarray
+    meta: dict = dataclasses.field(default_factory=dict)
+
+
+def dense_shell_field(N: int, amplitude: float = 0.08, seed: int = SEED_GRID, r0: float = 0.6,
+                      base_freq: float = 4.0, sigma_max: float = 1000.0, haze: float = 0.2,
+                      n_blobs: int = 12, blob_r: float = 0.08) -> DenseField:
+    """Stand-in for a trained NeRF evaluated on the full N^3 grid: an opaque
+    displaced shell (the surface of shell_grid, density a tent of height
+    sigma_max three voxels wide), n_blobs dense balls inside it that no
+    outside camera can see, and a faint haze everywhere (alpha below the
+    empty-space threshold at the paper's grid sizes).  Colour and features
+    follow the same hash as shell_grid's bytes, divided by 255."""
+    lib = _shellgen()
+    sigma = np.empty((N, N, N), np.float32)
+    rgb = np.empty((N, N, N, 3), np.float32)
+    feat = np.empty((N, N, N, 4), np.float32)
+    rc = lib.shellgen_dense(N, r0, amplitude, base_freq, seed, seed + 1000, sigma_max, haze, n_blobs, blob_r,
+                            sigma.ctypes.data, rgb.ctypes.data, feat.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"dense field generator failed ({rc})")
+    return DenseField(N, sigma, rgb, feat, meta=dict(kind="dense_shell", seed=seed, amplitude=amplitude, r0=r0,
+                                                     sigma_max=sigma_max, haze=haze, n_blobs=n_blobs,
+                                                     blob_r=blob_r))
 
 
 # --------------------------------------------------------------------------- cameras

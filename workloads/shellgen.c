@@ -237,3 +237,64 @@ int shellgen_fill(int32_t N, int32_t B, double r0, double A, double f0, uint64_t
     tables_free(&p);
     return err;
 }
+
+/*
+ * Dense synthetic radiance field for the baking workload (the input of the
+ * paper's Section 5.3, which evaluates NeRF densely on the N^3 grid): float
+ * density, colour and features for every voxel, x fastest.
+ *   sigma = sigma_max * max(0, 1 - |s|/3)      around the shell surface
+ *         + sigma_max / 4 inside each of n_blobs balls of radius blob_r whose
+ *           centres lie at radius < 0.3 (occluded by the shell)
+ *         + haze                                everywhere
+ *   rgb, feat = the colour/feature bytes of shellgen_fill / 255.
+ */
+int shellgen_dense(int32_t N, double r0, double A, double f0, uint64_t seed, uint64_t color_seed,
+                   double sigma_max, double haze, int32_t n_blobs, double blob_r, float *sigma, float *rgb,
+                   float *feat)
+{
+    shell_params p;
+    memset(&p, 0, sizeof p);
+    p.N = N; p.B = 1; p.r0 = r0; p.A = A; p.f0 = f0; p.seed = seed;
+    if (tables_init(&p)) return -1;
+    double cx[64], cy[64], cz[64];
+    if (n_blobs > 64) n_blobs = 64;
+    for (int b = 0; b < n_blobs; ++b) {
+        uint64_t h = hash4(seed, 77, b, 0, 0);
+        double u0 = (double)(h & 0xFFFFF) / 1048576.0, u1 = (double)((h >> 20) & 0xFFFFF) / 1048576.0;
+        double u2 = (double)((h >> 40) & 0xFFFFF) / 1048576.0;
+        double rr = 0.3 * cbrt(u2), th = acos(1.0 - 2.0 * u0), ph = 6.283185307179586 * u1;
+        cx[b] = rr * sin(th) * cos(ph); cy[b] = rr * sin(th) * sin(ph); cz[b] = rr * cos(th);
+    }
+    const double v = 2.0 / (double)N;
+    const double amp = A * 1.75;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t gz = 0; gz < N; ++gz)
+        for (int64_t gy = 0; gy < N; ++gy)
+            for (int64_t gx = 0; gx < N; ++gx) {
+                int64_t vi = (gz * N + gy) * N + gx;
+                double x = ((double)gx + 0.5) * v - 1.0, y = ((double)gy + 0.5) * v - 1.0;
+                double z = ((double)gz + 0.5) * v - 1.0;
+                double len = sqrt(x * x + y * y + z * z);
+                double s = haze;
+                if (len > 1e-12 && len >= r0 - amp - 3.0 * v && len <= r0 + amp + 3.0 * v) {
+                    double ux = x / len, uy = y / len, uz = z / len, r = r0, wgt = 1.0;
+                    for (int o = 0; o < N_OCT; ++o) {
+                        double F = f0 * (double)(1 << o);
+                        r += A * wgt * value_noise(&p.oct[o], F * ux, F * uy, F * uz);
+                        wgt *= 0.5;
+                    }
+                    double d = fabs((len - r) / v);
+                    if (d < 3.0) s += sigma_max * (1.0 - d / 3.0);
+                }
+                for (int b = 0; b < n_blobs; ++b) {
+                    double dx = x - cx[b], dy = y - cy[b], dz = z - cz[b];
+                    if (dx * dx + dy * dy + dz * dz < blob_r * blob_r) s += 0.25 * sigma_max;
+                }
+                sigma[vi] = (float)s;
+                uint64_t h = hash4(color_seed, 9, gx, gy, gz);
+                for (int c = 0; c < 3; ++c) rgb[vi * 3 + c] = (float)((h >> (8 * c)) & 0xFF) / 255.0f;
+                for (int c = 0; c < 4; ++c) feat[vi * 4 + c] = (float)((h >> (8 * (c + 3))) & 0xFF) / 255.0f;
+            }
+    tables_free(&p);
+    return 0;
+}
