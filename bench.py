@@ -1,6 +1,6 @@
 """Throughput of the SNeRG render path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs plain,batched,adjoint,large,finetune,nondeferred]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs plain,batched,adjoint,large,finetune,nondeferred,bake]
     python bench.py --legs plain,copy --no-cpu-baseline   # adds the copy-kernel calibration launches
     python bench.py --source-hash                          # hash of the render kernel sources
 
@@ -14,7 +14,9 @@ with its max-abs error against the FP64 oracle, the adjoint (8 views at
 large case (64 x 1920x1080 in one launch, then 65,536-ray minibatch forward
 + backward), and fine-tuning of the deferred network on the fixed uint8
 grid (render, squared error, MLP backward, Adam per 65,536-ray step), and
-the non-deferred ablation (the network on every sample, FP32 and FP16 MFMA).
+the non-deferred ablation (the network on every sample, FP32 and FP16 MFMA),
+and baking a dense 512^3 field (both culls from 100 training views at
+800x800, then the 8-bit atlas).
 Prints one JSON line on stdout; progress goes to stderr.
 
 roofline.traffic is the measured HBM traffic of one render launch, read from
@@ -362,6 +364,52 @@ def leg_finetune(args, torch, S, W):
     return res
 
 
+def leg_bake(args, torch, S, W):
+    """Baking (Section 5.3, 5.4) of a dense 512^3 field (opaque displaced
+    shell, hidden interior blobs, faint haze; B = 32) from the 100 training
+    views of a synthetic scene (800x800, 39 degrees, eyes on a sphere of
+    radius 2): the empty-space and visibility culls (snerg_bake_cull, which
+    reads the kept count back) and the 8-bit atlas of the kept blocks
+    (snerg_bake_quantize).  Rates: voxels of the dense grid and training
+    rays per second over the whole bake; the quantisation's HBM rate from
+    its algorithmic bytes (32 B read, 8 B written per kept voxel)."""
+    N, B = 512, 32
+    f = W.dense_shell_field(N)
+    sg = torch.from_numpy(f.sigma).cuda()
+    rg = torch.from_numpy(f.rgb).cuda()
+    ft = torch.from_numpy(f.feat).cuda()
+    del f
+    cams = W.sphere_cameras([(800, 800, 39.0)] * 100, seed=1)
+    rays = sum(c.n_rays for c in cams)
+    h = S.Handle()
+    carr = S.make_cameras(cams)
+    opts = S.make_bake_opts()
+    G3 = (N // B) ** 3
+    ind = torch.empty(G3, dtype=torch.int32, device="cuda")
+    n_kept = [0]
+
+    def cull():
+        n_kept[0] = S.snerg_bake_cull(h, N, B, sg, carr, opts, ind)
+
+    reps = max(3, args.steps // 4)
+    ms_cull = time_launches(cull, reps, 1, torch)
+    n = n_kept[0]
+    d8 = torch.empty((n, B, B, B), dtype=torch.uint8, device="cuda")
+    r8 = torch.empty((n, B, B, B, 3), dtype=torch.uint8, device="cuda")
+    f8 = torch.empty((n, B, B, B, 4), dtype=torch.uint8, device="cuda")
+    ms_q = time_launches(lambda: S.snerg_bake_quantize(h, N, B, sg, rg, ft, ind, n, opts, d8, r8, f8),
+                         max(5, args.steps), 2, torch)
+    q_bytes = n * B ** 3 * 40
+    ms = ms_cull + ms_q
+    res = dict(ms=ms, ms_cull=ms_cull, ms_quantize=ms_q, gvox_per_s=N ** 3 / (ms * 1e-3) / 1e9,
+               training_mrays=rays / ms_cull / 1e3, training_rays=rays, kept_blocks=n, blocks=G3,
+               quantize_gbs=q_bytes / (ms_q * 1e-3) / 1e9, quantize_frac_hbm=q_bytes / (ms_q * 1e-3) / 1e9 / HBM_PEAK_GBS)
+    log(f"bake 512^3: cull {ms_cull:.2f} ms ({res['training_mrays']:.0f} training Mrays/s), quantise {ms_q:.3f} ms "
+        f"({res['quantize_gbs']:.0f} GB/s), kept {n}/{G3} blocks")
+    del sg, rg, ft
+    return res
+
+
 def leg_copy(torch):
     """A plain 1 GiB device-to-device copy (torch's elementwise copy kernel),
     launched three times: what FETCH_SIZE and WRITE_SIZE read for it against
@@ -399,7 +447,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--legs", default="plain,batched,adjoint,large,finetune,nondeferred")
+    ap.add_argument("--legs", default="plain,batched,adjoint,large,finetune,nondeferred,bake")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--source-hash", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
@@ -431,6 +479,8 @@ def main():
         extra["finetune"] = leg_finetune(args, torch, S, W)
     if "nondeferred" in legs:
         extra["nondeferred"] = leg_nondeferred(args, torch, S, W, plain)
+    if "bake" in legs:
+        extra["bake"] = leg_bake(args, torch, S, W)
     if "copy" in legs:
         extra["copy"] = leg_copy(torch)
 
@@ -488,6 +538,8 @@ def main():
     if "finetune" in extra:
         f = extra["finetune"]
         legs_out["finetune_mlp_512"] = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in f.items()}
+    if "bake" in extra:
+        legs_out["bake_512"] = {k: (round(v, 5) if isinstance(v, float) else v) for k, v in extra["bake"].items()}
     if "copy" in extra:
         legs_out["copy_calibration"] = {k: round(v, 4) for k, v in extra["copy"].items()}
     line["legs"] = legs_out

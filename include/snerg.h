@@ -260,6 +260,64 @@ typedef struct {
 int snerg_adam_step(snerg_handle *h, float *param, const float *grad, float *m, float *v, int64_t n,
                     const snerg_adam *cfg, void *stream);
 
+/* ---------------------------------------------------------------- baking */
+
+/* Thresholds of the baking culls (Section 5.3) and the density scale of the
+ * 8-bit quantisation (Section 5.4). */
+typedef struct {
+    float tau_alpha;   /* empty-space cull: keep a macroblock whose largest voxel alpha is >= this (0.005) */
+    float tau_vis;     /* visibility cull: keep a macroblock whose largest voxel visibility is >= this (0.01) */
+    float sigma_scale; /* density byte = rint(sigma * (255 / sigma_scale)); the grid's sigma_scale (50) */
+    int32_t reserved;
+} snerg_bake_opts;
+
+/*
+ * Macroblock culling of a densely evaluated field (Section 5.3): a
+ * macroblock is stored only if it is both non-empty and visible from at
+ * least one training view.
+ *  - sigma: device float32 [N^3] (x fastest), the density of every voxel
+ *    per unit length of the world box (finite, >= 0).  N and B obey the
+ *    limits of the grid struct above (N/B <= 64).
+ *  - Opacity of a voxel: alpha = 1 - exp(-sigma v), v = 1/N.  A macroblock
+ *    passes the empty-space cull when its largest alpha is >= tau_alpha.
+ *  - Visibility of a voxel: the largest transmittance between it and any
+ *    training camera.  Every pixel ray of `cams` (host, the training views)
+ *    is marched on the render's sample lattice (geometry above, step
+ *    delta = 1/N); sample k lies in voxel floor(P_k / 2^16), reads that
+ *    voxel's density and sees T_k = exp(-delta * S_k), S_k the sum of the
+ *    densities of the ray's earlier samples inside the grid (summed in
+ *    float64 in sample order).  A macroblock passes the visibility cull
+ *    when some sample inside it has T_k >= tau_vis.  Both tests are decided
+ *    on the exact equivalents max sigma >= -N log(1 - tau_alpha) and
+ *    min S_k <= -N log(tau_vis), in float64.
+ *  - Outputs (device): indirection int32 [(N/B)^3], -1 for a culled
+ *    macroblock, else its atlas id, kept blocks numbered 0, 1, ... in
+ *    indirection order; block_alpha and block_vis (nullable) float32
+ *    [(N/B)^3], the largest voxel alpha and the largest visibility (0 when
+ *    below tau_vis).  *n_blocks (host) receives the number of kept blocks.
+ * Synchronises `stream` (the count is read back).
+ */
+int snerg_bake_cull(snerg_handle *h, int32_t N, int32_t B, const float *sigma, const snerg_camera *cams,
+                    int32_t n_cams, const snerg_bake_opts *opts, float *block_alpha, float *block_vis,
+                    int32_t *indirection, int32_t *n_blocks, void *stream);
+
+/*
+ * 8-bit canonical atlas of the kept macroblocks (Section 5.4: every baked
+ * value is stored in 8 bits): density byte rint(sigma * k) with
+ * k = 255 / sigma_scale, colour and feature bytes rint(255 c), each a single
+ * float32 multiplication rounded half to even and clamped to [0, 255] (NaN
+ * to 0).  sigma [N^3], rgb [N^3][3], feat [N^3][4]: device float32, x
+ * fastest.  indirection: device int32 [(N/B)^3] with atlas ids in
+ * [0, n_blocks), each at most once (as written by snerg_bake_cull); an atlas
+ * block no entry names is written as zeros.  dens8 [n_blocks][B][B][B],
+ * rgb8 [n_blocks][B][B][B][3], feat8 [n_blocks][B][B][B][4]: device, the
+ * canonical layout snerg_pack_grid takes with SNERG_U8.
+ */
+int snerg_bake_quantize(snerg_handle *h, int32_t N, int32_t B, const float *sigma, const float *rgb,
+                        const float *feat, const int32_t *indirection, int32_t n_blocks,
+                        const snerg_bake_opts *opts, uint8_t *dens8, uint8_t *rgb8, uint8_t *feat8,
+                        void *stream);
+
 /* ---------------------------------------------------------------- tuning */
 
 int snerg_set_tuning(snerg_handle *h, const snerg_tuning *t);

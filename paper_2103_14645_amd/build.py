@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsnerg.so")
 OBJ_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["api.cpp", "pack.hip", "render.hip", "render_ps.hip", "backward.hip", "train.hip"]
+SOURCES = ["api.cpp", "pack.hip", "render.hip", "render_ps.hip", "backward.hip", "train.hip", "bake.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

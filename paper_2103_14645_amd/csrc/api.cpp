@@ -153,6 +153,9 @@ struct snerg_handle {
     size_t partial_cap = 0;
     float* d_gcv = nullptr;  // per-ray g_C, g_V of the backward pass
     size_t gcv_cap = 0;
+    float* d_bake = nullptr;  // baking scratch: per-block max density, visibility words, atlas map
+    size_t bake_cap = 0;      // in floats
+    int32_t* h_bake_count = nullptr;  // pinned: kept-block count read back by snerg_bake_cull
     snerg_tuning tuning = {8, 8, 4, 8};
     // cached graph of {counter reset, persistent render}
     hipGraphExec_t graph_exec = nullptr;
@@ -355,6 +358,8 @@ int snerg_destroy(snerg_handle* h) {
     if (h->d_counter) hipFree(h->d_counter);
     if (h->d_partial) hipFree(h->d_partial);
     if (h->d_gcv) hipFree(h->d_gcv);
+    if (h->d_bake) hipFree(h->d_bake);
+    if (h->h_bake_count) hipHostFree(h->h_bake_count);
     if (h->cams_copied) hipEventDestroy(h->cams_copied);
     if (h->cap_stream) hipStreamDestroy(h->cap_stream);
     delete h;
@@ -527,6 +532,138 @@ int snerg_adam_step(snerg_handle* h, float* param, const float* grad, float* m, 
     const float c2 = float(1.0 - std::pow(double(cfg->beta2), double(cfg->step)));
     HIP_TRY(launch_adam(param, grad, m, v, n, cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, c1, c2,
                         static_cast<hipStream_t>(stream)));
+    return SNERG_OK;
+}
+
+namespace {
+
+int check_bake(int32_t N, int32_t B, const snerg_bake_opts* o) {
+    if (!o) return fail(SNERG_ERR_INVALID_ARG, "opts is NULL");
+    int rc = check_shape(N, B, 0, SNERG_U8);
+    if (rc) return rc;
+    if (!(o->tau_alpha >= 0.0f && o->tau_alpha < 1.0f)) return fail(SNERG_ERR_INVALID_ARG, "tau_alpha must lie in [0, 1)");
+    if (!(o->tau_vis > 0.0f && o->tau_vis <= 1.0f)) return fail(SNERG_ERR_INVALID_ARG, "tau_vis must lie in (0, 1]");
+    if (!std::isfinite(o->sigma_scale) || o->sigma_scale <= 0.0f)
+        return fail(SNERG_ERR_INVALID_ARG, "sigma_scale must be finite and > 0");
+    return SNERG_OK;
+}
+
+bool aligned(const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
+
+int log2i(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+// Handle-owned baking scratch for G3 macroblocks (grown on demand): the
+// per-block largest density (float), visibility words (uint64), the
+// kept-block count and the atlas-id map (int32).
+struct BakeScratch {
+    float* bmax;
+    uint64_t* depth_bits;
+    int32_t* count;
+    int32_t* lin_of;
+};
+
+int bake_scratch(snerg_handle* h, int64_t G3, BakeScratch* out) {
+    const size_t off_depth = (size_t(G3) + 1) & ~size_t(1);  // in 4-byte words, 8-byte aligned
+    const size_t off_count = off_depth + 2 * size_t(G3);
+    const size_t off_map = off_count + 2;
+    const size_t need = off_map + size_t(G3);
+    if (need > h->bake_cap) {
+        HIP_TRY(hipDeviceSynchronize());
+        if (h->d_bake) HIP_TRY(hipFree(h->d_bake));
+        h->d_bake = nullptr;
+        h->bake_cap = 0;
+        HIP_TRY(hipMalloc(&h->d_bake, need * sizeof(float)));
+        h->bake_cap = need;
+    }
+    out->bmax = h->d_bake;
+    out->depth_bits = reinterpret_cast<uint64_t*>(h->d_bake + off_depth);
+    out->count = reinterpret_cast<int32_t*>(h->d_bake + off_count);
+    out->lin_of = reinterpret_cast<int32_t*>(h->d_bake + off_map);
+    return SNERG_OK;
+}
+
+}  // namespace
+
+int snerg_bake_cull(snerg_handle* h, int32_t N, int32_t B, const float* sigma, const snerg_camera* cams,
+                    int32_t n_cams, const snerg_bake_opts* opts, float* block_alpha, float* block_vis,
+                    int32_t* indirection, int32_t* n_blocks, void* stream) {
+    int rc = check_bake(N, B, opts);
+    if (rc) return rc;
+    int64_t total = 0;
+    if ((rc = check_cams(cams, n_cams, &total))) return rc;
+    if (!sigma || !indirection || !n_blocks) return fail(SNERG_ERR_INVALID_ARG, "sigma/indirection/n_blocks is NULL");
+    if (!h) return fail(SNERG_ERR_INVALID_ARG, "handle is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t G = N / B, G3 = G * G * G;
+    BakeScratch sc;
+    if ((rc = bake_scratch(h, G3, &sc))) return rc;
+    if (!h->h_bake_count) HIP_TRY(hipHostMalloc(&h->h_bake_count, 256, hipHostMallocDefault));
+    int64_t total_tiles = 0;
+    rc = upload_cams(h, cams, n_cams, h->tuning.tile_w, h->tuning.tile_h, s, &total_tiles);
+    if (rc) return rc;
+    BakeCullPlan p;
+    p.sigma = sigma;
+    p.cams = h->d_cams;
+    p.n_cams = n_cams;
+    p.N = N;
+    p.logB = log2i(B);
+    p.G = int32_t(G);
+    p.total_tiles = total_tiles;
+    p.tile_w = h->tuning.tile_w;
+    p.tile_h = h->tuning.tile_h;
+    p.vec4 = B >= 4 && aligned(sigma, 16);
+    // alpha = 1 - exp(-sigma / N) >= tau_alpha  <=>  sigma >= -N log(1 - tau_alpha)
+    p.sigma_thr = -double(N) * std::log1p(-double(opts->tau_alpha));
+    // T = exp(-S / N) >= tau_vis  <=>  S <= -N log(tau_vis), S the density prefix sum
+    p.sum_thr = -double(N) * std::log(double(opts->tau_vis));
+    p.bmax = sc.bmax;
+    p.depth_bits = sc.depth_bits;
+    p.block_alpha = block_alpha;
+    p.block_vis = block_vis;
+    p.indirection = indirection;
+    p.n_blocks_dev = sc.count;
+    HIP_TRY(launch_bake_cull(p, s));
+    HIP_TRY(hipMemcpyAsync(h->h_bake_count, p.n_blocks_dev, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *n_blocks = *h->h_bake_count;
+    return SNERG_OK;
+}
+
+int snerg_bake_quantize(snerg_handle* h, int32_t N, int32_t B, const float* sigma, const float* rgb, const float* feat,
+                        const int32_t* indirection, int32_t n_blocks, const snerg_bake_opts* opts, uint8_t* dens8,
+                        uint8_t* rgb8, uint8_t* feat8, void* stream) {
+    int rc = check_bake(N, B, opts);
+    if (rc) return rc;
+    const int64_t G = N / B, G3 = G * G * G;
+    if (n_blocks < 0 || n_blocks > G3) return fail(SNERG_ERR_INVALID_ARG, "n_blocks must lie in [0, (N/B)^3]");
+    if (n_blocks > 0 && (!sigma || !rgb || !feat || !indirection || !dens8 || !rgb8 || !feat8))
+        return fail(SNERG_ERR_INVALID_ARG, "an input or output pointer is NULL");
+    if (!h) return fail(SNERG_ERR_INVALID_ARG, "handle is NULL");
+    if (n_blocks == 0) return SNERG_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    BakeScratch sc;
+    if ((rc = bake_scratch(h, G3, &sc))) return rc;
+    BakeQuantPlan p;
+    p.sigma = sigma;
+    p.rgb = rgb;
+    p.feat = feat;
+    p.indirection = indirection;
+    p.n_blocks = n_blocks;
+    p.N = N;
+    p.logB = log2i(B);
+    p.G = int32_t(G);
+    p.vec4 = B >= 4 && aligned(sigma, 16) && aligned(rgb, 16) && aligned(feat, 16) && aligned(dens8, 4) &&
+             aligned(rgb8, 4) && aligned(feat8, 4);
+    p.k_sigma = 255.0f / opts->sigma_scale;
+    p.lin_of = sc.lin_of;
+    p.dens8 = dens8;
+    p.rgb8 = rgb8;
+    p.feat8 = feat8;
+    HIP_TRY(launch_bake_quantize(p, s));
     return SNERG_OK;
 }
 

@@ -59,6 +59,42 @@ struct BackwardArgs {
     int32_t mlp_only;      // MLP gradient only: no re-march
 };
 
+// Baking (Section 5.3, 5.4).
+struct BakeCullPlan {
+    const float* sigma;     // dense [N^3]
+    const DevCamera* cams;
+    int32_t n_cams;
+    int32_t N, logB, G;
+    int64_t total_tiles;    // training-ray tiles
+    int32_t tile_w, tile_h;
+    bool vec4;              // B >= 4 and sigma 16-byte aligned
+    double sigma_thr, sum_thr;
+    float* bmax;            // scratch [G^3]
+    uint64_t* depth_bits;   // scratch [G^3]
+    float* block_alpha;     // nullable
+    float* block_vis;       // nullable
+    int32_t* indirection;
+    int32_t* n_blocks_dev;
+};
+
+struct BakeQuantPlan {
+    const float* sigma;
+    const float* rgb;
+    const float* feat;
+    const int32_t* indirection;
+    int32_t n_blocks;
+    int32_t N, logB, G;
+    bool vec4;              // B >= 4, inputs 16-byte and outputs 4-byte aligned
+    float k_sigma;
+    int32_t* lin_of;        // scratch [n_blocks]
+    uint8_t* dens8;
+    uint8_t* rgb8;
+    uint8_t* feat8;
+};
+
+hipError_t launch_bake_cull(const BakeCullPlan& p, hipStream_t s);
+hipError_t launch_bake_quantize(const BakeQuantPlan& p, hipStream_t s);
+
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_pack(const PackedLayout& L, int32_t n_blocks, bool f32, const int32_t* ind,

@@ -72,6 +72,11 @@ class snerg_adam(ctypes.Structure):
                 ("eps", ctypes.c_float), ("step", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class snerg_bake_opts(ctypes.Structure):
+    _fields_ = [("tau_alpha", ctypes.c_float), ("tau_vis", ctypes.c_float), ("sigma_scale", ctypes.c_float),
+                ("reserved", ctypes.c_int32)]
+
+
 class snerg_tuning(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
                 ("waves_per_group", ctypes.c_int32), ("groups_per_cu", ctypes.c_int32)]
@@ -105,6 +110,8 @@ def lib():
             "snerg_autotune": [_P, _P, _P, _P, i32, _P, _P, i32, i32, _P, _P, _P, _P],
             "snerg_loss_mse": [_P, _P, _P, _P, i64, _P, _P, _P],
             "snerg_adam_step": [_P, _P, _P, _P, _P, i64, _P, _P],
+            "snerg_bake_cull": [_P, i32, i32, _P, _P, i32, _P, _P, _P, _P, _P, _P],
+            "snerg_bake_quantize": [_P, i32, i32, _P, _P, _P, _P, i32, _P, _P, _P, _P, _P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -120,7 +127,8 @@ def lib():
 
 EXPORTED = ["snerg_create", "snerg_destroy", "snerg_status_string", "snerg_last_error", "snerg_packed_size",
             "snerg_pack_grid", "snerg_render", "snerg_render_backward", "snerg_trace_visits",
-            "snerg_set_tuning", "snerg_get_tuning", "snerg_autotune", "snerg_loss_mse", "snerg_adam_step"]
+            "snerg_set_tuning", "snerg_get_tuning", "snerg_autotune", "snerg_loss_mse", "snerg_adam_step",
+            "snerg_bake_cull", "snerg_bake_quantize"]
 
 
 def _check(rc: int, what: str):
@@ -224,6 +232,27 @@ def snerg_adam_step(handle, param, grad, m, v, n, lr, step, beta1=0.9, beta2=0.9
     cfg = snerg_adam(float(lr), float(beta1), float(beta2), float(eps), int(step), 0)
     _check(lib().snerg_adam_step(handle.h, _ptr(param), _ptr(grad), _ptr(m), _ptr(v), int(n), ctypes.byref(cfg),
                                  _stream(stream)), "snerg_adam_step")
+
+
+def make_bake_opts(tau_alpha=0.005, tau_vis=0.01, sigma_scale=50.0):
+    return snerg_bake_opts(float(tau_alpha), float(tau_vis), float(sigma_scale), 0)
+
+
+def snerg_bake_cull(handle, N, B, sigma, cams, opts, indirection, block_alpha=None, block_vis=None,
+                    stream=None) -> int:
+    """Returns the number of kept macroblocks (synchronises the stream)."""
+    n = ctypes.c_int32(-1)
+    _check(lib().snerg_bake_cull(handle.h, int(N), int(B), _ptr(sigma), cams, len(cams), ctypes.byref(opts),
+                                 _ptr(block_alpha), _ptr(block_vis), _ptr(indirection), ctypes.byref(n),
+                                 _stream(stream)), "snerg_bake_cull")
+    return int(n.value)
+
+
+def snerg_bake_quantize(handle, N, B, sigma, rgb, feat, indirection, n_blocks, opts, dens8, rgb8, feat8,
+                        stream=None):
+    _check(lib().snerg_bake_quantize(handle.h, int(N), int(B), _ptr(sigma), _ptr(rgb), _ptr(feat),
+                                     _ptr(indirection), int(n_blocks), ctypes.byref(opts), _ptr(dens8), _ptr(rgb8),
+                                     _ptr(feat8), _stream(stream)), "snerg_bake_quantize")
 
 
 def snerg_trace_visits(handle, grid: snerg_grid, cams, ray_ids, n_rays, opts, max_visits, visits, counts,

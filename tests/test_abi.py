@@ -220,3 +220,34 @@ def test_per_sample_mlp_is_forward_only_without_aux():
     rc = lib.snerg_render_backward(None, ctypes.byref(f32), FAKE, cams, 1, None, 32, ctypes.byref(o), FAKE, FAKE,
                                    FAKE, FAKE, FAKE, FAKE, None)
     assert rc == S.SNERG_ERR_UNSUPPORTED and "PER_SAMPLE" in last_error()
+
+
+def test_bake_entry_point_validation():
+    lib = S.lib()
+    cams = (S.snerg_camera * 1)(good_camera())
+    ok = S.make_bake_opts()
+    cull = lambda N=64, B=8, o=ok, sg=FAKE, c=cams, nc=1, ind=FAKE: lib.snerg_bake_cull(
+        None, N, B, sg, c, nc, ctypes.byref(o) if o is not None else None, None, None, ind,
+        ctypes.byref(ctypes.c_int32()), None)
+    assert cull() == S.SNERG_ERR_INVALID_ARG and "handle" in last_error()       # got past every check
+    assert cull(o=None) == S.SNERG_ERR_INVALID_ARG
+    assert cull(B=6) == S.SNERG_ERR_UNSUPPORTED
+    assert cull(N=60) == S.SNERG_ERR_UNSUPPORTED
+    assert cull(N=4096, B=32) == S.SNERG_ERR_UNSUPPORTED                          # N/B > 64
+    for bad in (S.make_bake_opts(tau_alpha=1.0), S.make_bake_opts(tau_alpha=-0.1), S.make_bake_opts(tau_vis=0.0),
+                S.make_bake_opts(tau_vis=1.5), S.make_bake_opts(tau_vis=float("nan")),
+                S.make_bake_opts(sigma_scale=0.0), S.make_bake_opts(sigma_scale=float("inf"))):
+        assert cull(o=bad) == S.SNERG_ERR_INVALID_ARG
+    assert cull(sg=None) == S.SNERG_ERR_INVALID_ARG and "sigma" in last_error()
+    assert cull(ind=None) == S.SNERG_ERR_INVALID_ARG
+    assert cull(nc=0) == S.SNERG_ERR_INVALID_ARG
+    assert cull(c=None) == S.SNERG_ERR_INVALID_ARG
+    quant = lambda n=4, o=ok, sg=FAKE, out=FAKE: lib.snerg_bake_quantize(
+        None, 64, 8, sg, FAKE, FAKE, FAKE, n, ctypes.byref(o), out, FAKE, FAKE, None)
+    assert quant() == S.SNERG_ERR_INVALID_ARG and "handle" in last_error()
+    assert quant(n=-1) == S.SNERG_ERR_INVALID_ARG
+    assert quant(n=513) == S.SNERG_ERR_INVALID_ARG                               # more than (N/B)^3
+    assert quant(sg=None) == S.SNERG_ERR_INVALID_ARG and "NULL" in last_error()
+    assert quant(out=None) == S.SNERG_ERR_INVALID_ARG and "NULL" in last_error()
+    assert quant(n=0, sg=None, out=None) == S.SNERG_ERR_INVALID_ARG and "handle" in last_error()
+    assert quant(o=S.make_bake_opts(sigma_scale=-1.0)) == S.SNERG_ERR_INVALID_ARG
