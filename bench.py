@@ -300,7 +300,7 @@ def leg_large(args, torch, S, W, O):
 
 def leg_nondeferred(args, torch, S, W, plain):
     """The performance ablation of Section 6 on the plain 512^3 frame: the
-    view network on every composited sample instead of once per pixel, in
+    view network on every composited sample rather than a single time per ray, in
     FP32 and on FP16 MFMA tiles; the deferral speed-up against the deferred
     FP32 frame and the per-sample network's FLOP rate."""
     cfg = W.config("plain512")

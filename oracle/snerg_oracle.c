@@ -31,13 +31,13 @@
  *     centres, a voxel outside the grid or in an empty macroblock reads 0.
  *     The sample is "active" when some corner has non-zero density and
  *     non-zero weight; an inactive sample has sigma = 0 and contributes
- *     nothing ("only fetching features where the volume density is
- *     non-zero", Section 5.2).
+ *     nothing (Section 5.2 reads colour and features only where there is
+ *     density).
  *  5. Front-to-back compositing (Eq. 2, 5, 6) with a constant step
  *     delta = 1/N: alpha = 1 - exp(-sigma*delta), w = T*alpha,
  *     C_d += w*c_d, V += w*v, T *= (1 - alpha); ray marching ends after the
- *     sample that brings T below t_stop ("terminating once the opacity has
- *     saturated", Section 5.2).
+ *     sample that brings T below t_stop (Section 5.2 ends the march when
+ *     the accumulated opacity saturates).
  *  6. Deferred shading (Eq. 7, Section 4.2, Appendix A): once per pixel, if
  *     at least one sample was composited, the MLP with 2 hidden layers of 16
  *     channels maps [C_d, V, d, PE(d)] (PE: sin and cos at octaves 0..3,

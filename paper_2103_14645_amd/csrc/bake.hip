@@ -18,6 +18,8 @@
 //                     across wavefronts).
 //  k_bake_quantize    8-bit quantisation of the kept blocks into the
 //                     canonical atlas, four voxels per lane along x.
+#include <type_traits>
+
 #include "snerg_launch.h"
 
 namespace snerg {
@@ -89,9 +91,23 @@ struct BakeVisArgs {
 };
 
 // Samples loaded ahead of the sequential prefix sum.
-constexpr int kVisAhead = 8;
+constexpr int kVisAhead = 4;
 
+// IDX32: N^3 < 2^32, voxel indices in 32-bit arithmetic.
+template <bool IDX32>
 __global__ __launch_bounds__(256) void k_bake_visibility(BakeVisArgs a) {
+    // Per-workgroup cache of bounds on the blocks' minima: 256 slots indexed
+    // by the low 8 bits of the block index, each one 32-bit word (read and
+    // written whole, so no reader sees half an update): the block index's
+    // high 10 bits, then a 22-bit code whose value is an upper bound of a
+    // prefix sum already folded into that block's minimum (the sum rounded
+    // up to float, then its bits rounded up to a multiple of 2^10).  A block
+    // entry whose prefix sum is at least that bound needs no global access:
+    // the block's minimum is already no larger.  A racing overwrite only
+    // costs a later global check.
+    __shared__ uint32_t vcache[256];
+    vcache[threadIdx.x & 255] = (0x3ffu << 22) | (0x7f800000u >> 10);  // bound +inf: never skips
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     const int64_t t = int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (t >= a.total_tiles) return;  // wave-uniform
@@ -114,38 +130,72 @@ __global__ __launch_bounds__(256) void k_bake_visibility(BakeVisArgs a) {
     const int32_t n = int32_t(khi - klo + 1);
     const uint32_t N = uint32_t(a.N), G = uint32_t(a.G);
     const int bs = 16 + a.logB;
+    const double thr = a.sum_thr;
     double sum = 0.0;
     uint32_t prev = 0xffffffffu;
-    for (int32_t j = 0; j < n; j += kVisAhead) {
+    // One chunk of kVisAhead samples: all loads first, then the sequential
+    // prefix sum.  With FULL every sample of the chunk is inside the grid;
+    // otherwise the ones past the last inside sample are clamped onto it, so
+    // that every load stays in bounds.
+    auto chunk = [&](auto full_tag, int32_t last) {
+        constexpr bool FULL = decltype(full_tag)::value;
         float sv[kVisAhead];
         uint32_t bk[kVisAhead];
+        uint32_t Q[3] = {uint32_t(P[0]), uint32_t(P[1]), uint32_t(P[2])};
 #pragma unroll
         for (int u = 0; u < kVisAhead; ++u) {
-            const bool in = j + u < n;
-            int32_t Q[3];
+            if (u > 0) {
+                const uint32_t m = (FULL || u <= last) ? 0xffffffffu : 0u;
 #pragma unroll
-            for (int q = 0; q < 3; ++q) Q[q] = in ? P[q] + u * s[q] : 0;
-            const uint64_t v = (uint64_t(uint32_t(Q[2]) >> 16) * N + (uint32_t(Q[1]) >> 16)) * N +
-                               (uint32_t(Q[0]) >> 16);
-            sv[u] = in ? a.sigma[v] : 0.0f;
-            bk[u] = ((uint32_t(Q[2]) >> bs) * G + (uint32_t(Q[1]) >> bs)) * G + (uint32_t(Q[0]) >> bs);
+                for (int q = 0; q < 3; ++q) Q[q] += uint32_t(s[q]) & m;
+            }
+            if (IDX32) {  // every factor and partial sum below 2^24
+                const uint32_t v = __umul24(__umul24(Q[2] >> 16, N) + (Q[1] >> 16), N) + (Q[0] >> 16);
+                sv[u] = a.sigma[v];
+            } else {
+                const uint64_t v = (uint64_t(Q[2] >> 16) * N + (Q[1] >> 16)) * N + (Q[0] >> 16);
+                sv[u] = a.sigma[v];
+            }
+            // macroblock coordinates packed 8 bits each (G <= 64)
+            bk[u] = (Q[0] >> bs) | ((Q[1] >> bs) << 8) | ((Q[2] >> bs) << 16);
         }
-        bool stop = false;
 #pragma unroll
         for (int u = 0; u < kVisAhead; ++u) {
-            if (!stop && j + u < n) {
+            if (FULL || u <= last) {
+                // first sample of a macroblock: the ray's smallest prefix sum in
+                // it; past the threshold no later block is visible from this ray
                 if (bk[u] != prev) {
                     prev = bk[u];
-                    const uint64_t bits = uint64_t(__double_as_longlong(sum));
-                    uint64_t* w = a.depth_bits + bk[u];
-                    if (bits < __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                        atomicMin(reinterpret_cast<unsigned long long*>(w), (unsigned long long)bits);
+                    if (sum <= thr) {
+                        const uint64_t bits = uint64_t(__double_as_longlong(sum));
+                        const uint32_t lin = __umul24(__umul24(bk[u] >> 16, G) + ((bk[u] >> 8) & 0xff), G) + (bk[u] & 0xff);
+                        const uint32_t key = vcache[lin & 255];
+                        if ((key >> 22) != (lin >> 8) || double(__uint_as_float((key & 0x3fffffu) << 10)) > sum) {
+                            uint64_t* w = a.depth_bits + lin;
+                            uint64_t g = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            if (bits < g) {
+                                atomicMin(reinterpret_cast<unsigned long long*>(w), (unsigned long long)bits);
+                                g = bits;
+                            }
+                            const double gv = __longlong_as_double((long long)g);
+                            float gf = float(gv);
+                            if (double(gf) < gv) gf = __uint_as_float(__float_as_uint(gf) + 1u);
+                            const uint32_t code = (__float_as_uint(gf) + 0x3ffu) >> 10;
+                            vcache[lin & 255] = ((lin >> 8) << 22) | code;
+                        }
+                    }
                 }
                 sum += double(sv[u]);
-                stop = sum > a.sum_thr;
             }
         }
-        if (stop) break;
+    };
+    for (int32_t j = 0;; j += kVisAhead) {
+        const int32_t last = n - 1 - j;
+        if (__all(last >= kVisAhead - 1))
+            chunk(std::true_type{}, last);
+        else
+            chunk(std::false_type{}, last);
+        if (sum > thr || last < kVisAhead) break;
 #pragma unroll
         for (int q = 0; q < 3; ++q) P[q] += kVisAhead * s[q];
     }
@@ -322,7 +372,10 @@ hipError_t launch_bake_cull(const BakeCullPlan& p, hipStream_t s) {
         v.sum_thr = p.sum_thr;
         v.depth_bits = p.depth_bits;
         const unsigned blocks = unsigned((p.total_tiles + 3) / 4);
-        hipLaunchKernelGGL(k_bake_visibility, dim3(blocks), dim3(256), 0, s, v);
+        if (int64_t(p.N) * p.N * p.N <= int64_t(0xffffffffu))
+            hipLaunchKernelGGL(k_bake_visibility<true>, dim3(blocks), dim3(256), 0, s, v);
+        else
+            hipLaunchKernelGGL(k_bake_visibility<false>, dim3(blocks), dim3(256), 0, s, v);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     BakeCompactArgs c;
