@@ -153,6 +153,8 @@ struct snerg_handle {
     size_t partial_cap = 0;
     float* d_gcv = nullptr;  // per-ray g_C, g_V of the backward pass
     size_t gcv_cap = 0;
+    float* d_tiles = nullptr;  // heavy-first tile order: order [tiles] int32, counts [32], classes [tiles] u8
+    size_t tiles_cap = 0;      // in floats
     float* d_bake = nullptr;  // baking scratch: per-block max density, visibility words, atlas map
     size_t bake_cap = 0;      // in floats
     int32_t* h_bake_count = nullptr;  // pinned: kept-block count read back by snerg_bake_cull
@@ -270,14 +272,23 @@ int render_impl(snerg_handle* h, const snerg_grid* grid, const float* mlp, const
         HIP_TRY(launch_render(a, vt, mlp_mode, wpg, 0, s));
         return SNERG_OK;
     }
+    // heavy-first tile order (scheduling only: every tile's result is unchanged)
+    const size_t order_words = size_t(total_tiles) + 2 * kCostClasses;
+    if ((rc = ensure_buffer(&h->d_tiles, &h->tiles_cap, order_words + (size_t(total_tiles) + 3) / 4))) return rc;
+    int32_t* order = reinterpret_cast<int32_t*>(h->d_tiles);
+    int32_t* counts = order + total_tiles;
+    uint8_t* cls = reinterpret_cast<uint8_t*>(h->d_tiles + order_words);
+    a.tile_order = order;
     if (!(opts->flags & SNERG_FLAG_PERSISTENT)) {
         a.mode = kModeTiles;
+        HIP_TRY(launch_tile_order(a, cls, counts, order, s));
         HIP_TRY(launch_render(a, vt, mlp_mode, wpg, 0, s));
         return SNERG_OK;
     }
     a.mode = kModePersistent;
     const int n_groups = h->n_cu * tu.groups_per_cu;
     if (!(opts->flags & SNERG_FLAG_GRAPH)) {
+        HIP_TRY(launch_tile_order(a, cls, counts, order, s));
         HIP_TRY(launch_fill_i32(h->d_counter, 1, 0, s));
         HIP_TRY(launch_render(a, vt, mlp_mode, wpg, n_groups, s));
         return SNERG_OK;
@@ -296,7 +307,8 @@ int render_impl(snerg_handle* h, const snerg_grid* grid, const float* mlp, const
         }
         hipGraph_t graph = nullptr;
         HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e1 = launch_fill_i32(h->d_counter, 1, 0, h->cap_stream);
+        hipError_t e1 = launch_tile_order(a, cls, counts, order, h->cap_stream);
+        if (e1 == hipSuccess) e1 = launch_fill_i32(h->d_counter, 1, 0, h->cap_stream);
         hipError_t e2 = e1 == hipSuccess ? launch_render(a, vt, mlp_mode, wpg, n_groups, h->cap_stream) : e1;
         hipError_t e3 = hipStreamEndCapture(h->cap_stream, &graph);
         if (e2 != hipSuccess) {
@@ -359,6 +371,7 @@ int snerg_destroy(snerg_handle* h) {
     if (h->d_partial) hipFree(h->d_partial);
     if (h->d_gcv) hipFree(h->d_gcv);
     if (h->d_bake) hipFree(h->d_bake);
+    if (h->d_tiles) hipFree(h->d_tiles);
     if (h->h_bake_count) hipHostFree(h->h_bake_count);
     if (h->cams_copied) hipEventDestroy(h->cams_copied);
     if (h->cap_stream) hipStreamDestroy(h->cap_stream);

@@ -265,6 +265,42 @@ __host__ __device__ __forceinline__ int64_t march_ray(const GridArgs& g, const u
     return -1;
 }
 
+// Occupied macroblocks on the ray's lattice inside the grid, up to `cap`:
+// the macroblock walk of march_ray alone, without visiting samples and
+// without early stop (a cost estimate for scheduling, not part of any
+// result).
+__device__ __forceinline__ int32_t occupied_blocks_on_ray(const GridArgs& g, const uint2* occ, const int64_t o[3],
+                                                          const int32_t s[3], int32_t cap) {
+    const int bs = 16 + g.logB;
+    const int64_t L = int64_t(g.N) << 16;
+    int64_t klo, khi;
+    if (!entry_range(o, s, L, klo, khi)) return 0;
+    float inv[3];
+    int32_t P[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int32_t sa = s[a] < 0 ? -s[a] : s[a];
+        inv[a] = sa != 0 ? 1.0f / float(sa) : 0.0f;
+        P[a] = int32_t(o[a] + klo * int64_t(s[a]));
+    }
+    const int32_t kend = int32_t(khi - klo);
+    int32_t k = 0, count = 0;
+    while (k <= kend && count < cap) {
+        int32_t b[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) b[a] = P[a] >> bs;
+        if ((unsigned)b[0] >= (unsigned)g.G || (unsigned)b[1] >= (unsigned)g.G || (unsigned)b[2] >= (unsigned)g.G)
+            break;
+        const int32_t nstep = block_steps(P, s, inv, b, bs);
+        const int32_t lin = (b[2] * g.G + b[1]) * g.G + b[0];
+        count += int32_t((occ[lin >> 5].x >> (lin & 31)) & 1u);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) P[a] += nstep * s[a];
+        k += nstep;
+    }
+    return count;
+}
+
 // The same visit sequence as march_ray, with both loops made convergent
 // across the wavefront: every lane runs one macroblock step per outer trip
 // and one in-block step per inner trip (lanes with nothing to do idle), and

@@ -178,7 +178,7 @@ __global__ __launch_bounds__(256) void k_render(RenderArgs a) {
             }
         } else {
             if (t >= a.total_tiles) break;  // wave-uniform; every wave reaches it
-            valid = tile_pixel(a, t, lane, ci, px, py, out_idx);
+            valid = tile_pixel(a, a.tile_order ? int64_t(a.tile_order[t]) : t, lane, ci, px, py, out_idx);
         }
         render_ray<VT, MLP>(a, occ, valid, ci, px, py, out_idx);
         if (!PERSIST) break;
@@ -240,6 +240,71 @@ __global__ __launch_bounds__(256) void k_trace(RenderArgs a) {
         cn[3] = n_act;
         cn[4] = int32_t(stop);
     }
+}
+
+// Heavy-first tile order.  A frame lasts as long as its slowest wavefronts
+// (tiles whose rays graze the surface and composite hundreds of samples);
+// issued late, they run on an emptying machine and set the frame time.
+// Tiles are therefore sorted by a cost class, the number of occupied
+// macroblocks on the tile's centre ray (capped at 15), and the render takes
+// them in decreasing class.  Pass 1: one lane per tile computes its class
+// and the class histogram.  Pass 2: each workgroup reserves, per class, a
+// range after all tiles of higher classes and writes its tiles there.
+__global__ __launch_bounds__(256) void k_tile_cost(RenderArgs a, uint8_t* __restrict__ cls,
+                                                   int32_t* __restrict__ counts) {
+    __shared__ int32_t hist[kCostClasses];
+    if (threadIdx.x < kCostClasses) hist[threadIdx.x] = 0;
+    const uint2* occ = stage_occupancy(a.grid);  // synchronises
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t < a.total_tiles) {
+        const int ci = find_camera_by_tile(a.cams, a.n_cams, t);
+        const DevCamera& c = a.cams[ci];
+        const int64_t tl = t - c.tile_offset;
+        const int tx = int(tl % c.tiles_x), ty = int(tl / c.tiles_x);
+        const int px = min(tx * a.tile_w + a.tile_w / 2, c.W - 1);
+        const int py = min(ty * a.tile_h + a.tile_h / 2, c.H - 1);
+        int64_t o[3];
+        int32_t sd[3];
+        float d[3];
+        ray_setup(c, a.grid.N, px, py, o, sd, d);
+        const int32_t k = occupied_blocks_on_ray(a.grid, occ, o, sd, kCostClasses - 1);
+        cls[t] = uint8_t(k);
+        atomicAdd(&hist[k], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < kCostClasses && hist[threadIdx.x] > 0) atomicAdd(&counts[threadIdx.x], hist[threadIdx.x]);
+}
+
+// counts[0..15]: class sizes; counts[16..31]: per-class cursors (zero).
+__global__ __launch_bounds__(256) void k_tile_sort(const uint8_t* __restrict__ cls, int32_t* __restrict__ counts,
+                                                   int64_t total, int32_t* __restrict__ order) {
+    __shared__ int32_t local[kCostClasses], base[kCostClasses];
+    if (threadIdx.x < kCostClasses) local[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int c = t < total ? int(cls[t]) : -1;
+    const int32_t pos = c >= 0 ? atomicAdd(&local[c], 1) : 0;
+    __syncthreads();
+    if (threadIdx.x < kCostClasses) {
+        int32_t off = 0;
+        for (int q = kCostClasses - 1; q > int(threadIdx.x); --q) off += counts[q];
+        const int32_t mine = local[threadIdx.x];
+        base[threadIdx.x] = off + (mine > 0 ? atomicAdd(&counts[kCostClasses + threadIdx.x], mine) : 0);
+    }
+    __syncthreads();
+    if (c >= 0) order[base[c] + pos] = int32_t(t);
+}
+
+hipError_t launch_tile_order(const RenderArgs& a, uint8_t* cls, int32_t* counts, int32_t* order, hipStream_t s) {
+    if (a.total_tiles <= 0) return hipSuccess;
+    hipError_t e = launch_fill_i32(counts, 2 * kCostClasses, 0, s);
+    if (e != hipSuccess) return e;
+    const unsigned blocks = unsigned((a.total_tiles + 255) / 256);
+    const size_t lds = size_t(a.grid.n_words) * sizeof(uint2);
+    hipLaunchKernelGGL(k_tile_cost, dim3(blocks), dim3(256), lds, s, a, cls, counts);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tile_sort, dim3(blocks), dim3(256), 0, s, cls, counts, a.total_tiles, order);
+    return hipGetLastError();
 }
 
 template <int VT, int MLP>

@@ -40,6 +40,7 @@ __device__ __forceinline__ bool locate_ps(const RenderArgs& a, int64_t t, int la
         px = int(local - int64_t(py) * a.cams[ci].W);
         return true;
     }
+    if (a.tile_order) t = a.tile_order[t];
     ci = find_camera_by_tile(a.cams, a.n_cams, t);
     const DevCamera& c = a.cams[ci];
     const int64_t tl = t - c.tile_offset;

@@ -29,6 +29,7 @@ struct RenderArgs {
     int64_t total_tiles;
     int32_t tile_w, tile_h;  // tile_w * tile_h == 64
     int32_t* tile_counter;   // persistent mode
+    const int32_t* tile_order;  // tile of each wavefront slot / queue entry (null: identity)
     float* out;              // [n][4]
     float* aux;              // [n][8] or null
     // visit tracing
@@ -105,6 +106,10 @@ hipError_t launch_pack(const PackedLayout& L, int32_t n_blocks, bool f32, const 
 hipError_t launch_render(const RenderArgs& a, int vt, int mlp_mode, int waves_per_group,
                          int n_groups, hipStream_t s);
 hipError_t launch_trace(const RenderArgs& a, int vt, hipStream_t s);
+// Heavy-first tile order for a tiled or persistent render: `cls` [total_tiles]
+// and `counts` [32] are scratch, `order` [total_tiles] receives the order.
+constexpr int kCostClasses = 16;
+hipError_t launch_tile_order(const RenderArgs& a, uint8_t* cls, int32_t* counts, int32_t* order, hipStream_t s);
 hipError_t launch_backward(const BackwardArgs& a, int n_groups, hipStream_t s);
 int backward_partial_rows(int n_groups);
 hipError_t launch_render_ps(const RenderArgs& a, int vt, bool f16, int wpg, int n_groups, hipStream_t s);
