@@ -335,6 +335,21 @@ int snerg_autotune(snerg_handle *h, const snerg_grid *grid, const float *mlp,
                    const snerg_tuning *candidates, int32_t n_candidates, int32_t reps,
                    float *out_rgba, snerg_tuning *best, float *best_ms, void *stream);
 
+/* ----------------------------------------------------------- measurement */
+
+/*
+ * Kernel timing for measurement.  While enabled, every snerg_render
+ * records a pair of HIP events on its stream around its render kernel
+ * alone (after the tile-order pre-pass; around the whole replay in graph
+ * mode) into a ring that keeps the last 256 renders.  snerg_timing_enable
+ * with on != 0 empties the ring; on = 0 stops recording.
+ * snerg_timing_read synchronises the recorded events and writes up to
+ * `max` kernel times in milliseconds, oldest first, to ms (host), and the
+ * number written to *n.
+ */
+int snerg_timing_enable(snerg_handle *h, int32_t on);
+int snerg_timing_read(snerg_handle *h, float *ms, int32_t max, int32_t *n);
+
 #ifdef __cplusplus
 }
 #endif

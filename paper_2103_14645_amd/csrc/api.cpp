@@ -158,6 +158,10 @@ struct snerg_handle {
     float* d_bake = nullptr;  // baking scratch: per-block max density, visibility words, atlas map
     size_t bake_cap = 0;      // in floats
     int32_t* h_bake_count = nullptr;  // pinned: kept-block count read back by snerg_bake_cull
+    // kernel timing ring (measurement aid)
+    bool timing = false;
+    std::vector<hipEvent_t> t_start, t_stop;
+    int64_t t_count = 0;
     snerg_tuning tuning = {8, 8, 4, 8};
     // cached graph of {counter reset, persistent render}
     hipGraphExec_t graph_exec = nullptr;
@@ -243,6 +247,20 @@ int common_render_checks(const snerg_grid* grid, const float* mlp, bool need_mlp
     return SNERG_OK;
 }
 
+constexpr int kTimingRing = 256;
+
+// Events around the render kernel when timing is enabled (no-ops otherwise).
+hipError_t timing_begin(snerg_handle* h, hipStream_t s) {
+    if (!h->timing) return hipSuccess;
+    return hipEventRecord(h->t_start[size_t(h->t_count % kTimingRing)], s);
+}
+hipError_t timing_end(snerg_handle* h, hipStream_t s) {
+    if (!h->timing) return hipSuccess;
+    hipError_t e = hipEventRecord(h->t_stop[size_t(h->t_count % kTimingRing)], s);
+    ++h->t_count;
+    return e;
+}
+
 int render_impl(snerg_handle* h, const snerg_grid* grid, const float* mlp, const snerg_camera* cams,
                 int32_t n_cams, const int64_t* ray_ids, int64_t n_rays, const snerg_opts* opts,
                 float* out_rgba, float* aux, hipStream_t s, const snerg_tuning& tu) {
@@ -269,7 +287,9 @@ int render_impl(snerg_handle* h, const snerg_grid* grid, const float* mlp, const
     const int wpg = tu.waves_per_group;
     if (ray_ids) {
         a.mode = kModeList;
+        HIP_TRY(timing_begin(h, s));
         HIP_TRY(launch_render(a, vt, mlp_mode, wpg, 0, s));
+        HIP_TRY(timing_end(h, s));
         return SNERG_OK;
     }
     // heavy-first tile order (scheduling only: every tile's result is unchanged)
@@ -282,7 +302,9 @@ int render_impl(snerg_handle* h, const snerg_grid* grid, const float* mlp, const
     if (!(opts->flags & SNERG_FLAG_PERSISTENT)) {
         a.mode = kModeTiles;
         HIP_TRY(launch_tile_order(a, cls, counts, order, s));
+        HIP_TRY(timing_begin(h, s));
         HIP_TRY(launch_render(a, vt, mlp_mode, wpg, 0, s));
+        HIP_TRY(timing_end(h, s));
         return SNERG_OK;
     }
     a.mode = kModePersistent;
@@ -290,7 +312,9 @@ int render_impl(snerg_handle* h, const snerg_grid* grid, const float* mlp, const
     if (!(opts->flags & SNERG_FLAG_GRAPH)) {
         HIP_TRY(launch_tile_order(a, cls, counts, order, s));
         HIP_TRY(launch_fill_i32(h->d_counter, 1, 0, s));
+        HIP_TRY(timing_begin(h, s));
         HIP_TRY(launch_render(a, vt, mlp_mode, wpg, n_groups, s));
+        HIP_TRY(timing_end(h, s));
         return SNERG_OK;
     }
     // Graph replay: the key is every launch parameter; the camera table's
@@ -321,7 +345,9 @@ int render_impl(snerg_handle* h, const snerg_grid* grid, const float* mlp, const
         HIP_TRY(e4);
         h->graph_key = key;
     }
+    HIP_TRY(timing_begin(h, s));
     HIP_TRY(hipGraphLaunch(h->graph_exec, s));
+    HIP_TRY(timing_end(h, s));
     return SNERG_OK;
 }
 
@@ -372,6 +398,8 @@ int snerg_destroy(snerg_handle* h) {
     if (h->d_gcv) hipFree(h->d_gcv);
     if (h->d_bake) hipFree(h->d_bake);
     if (h->d_tiles) hipFree(h->d_tiles);
+    for (hipEvent_t e : h->t_start) hipEventDestroy(e);
+    for (hipEvent_t e : h->t_stop) hipEventDestroy(e);
     if (h->h_bake_count) hipHostFree(h->h_bake_count);
     if (h->cams_copied) hipEventDestroy(h->cams_copied);
     if (h->cap_stream) hipStreamDestroy(h->cap_stream);
@@ -677,6 +705,36 @@ int snerg_bake_quantize(snerg_handle* h, int32_t N, int32_t B, const float* sigm
     p.rgb8 = rgb8;
     p.feat8 = feat8;
     HIP_TRY(launch_bake_quantize(p, s));
+    return SNERG_OK;
+}
+
+int snerg_timing_enable(snerg_handle* h, int32_t on) {
+    if (!h) return fail(SNERG_ERR_INVALID_ARG, "handle is NULL");
+    if (on && h->t_start.empty()) {
+        h->t_start.resize(kTimingRing, nullptr);
+        h->t_stop.resize(kTimingRing, nullptr);
+        for (int i = 0; i < kTimingRing; ++i) {
+            HIP_TRY(hipEventCreate(&h->t_start[size_t(i)]));
+            HIP_TRY(hipEventCreate(&h->t_stop[size_t(i)]));
+        }
+    }
+    h->timing = on != 0;
+    if (on) h->t_count = 0;
+    return SNERG_OK;
+}
+
+int snerg_timing_read(snerg_handle* h, float* ms, int32_t max, int32_t* n) {
+    if (!n || max < 0 || (max > 0 && !ms)) return fail(SNERG_ERR_INVALID_ARG, "ms/n is NULL or max < 0");
+    if (!h) return fail(SNERG_ERR_INVALID_ARG, "handle is NULL");
+    const int64_t have = std::min<int64_t>(h->t_count, kTimingRing);
+    const int64_t first = h->t_count - have;
+    int32_t w = 0;
+    for (int64_t i = first; i < h->t_count && w < max; ++i, ++w) {
+        const size_t j = size_t(i % kTimingRing);
+        HIP_TRY(hipEventSynchronize(h->t_stop[j]));
+        HIP_TRY(hipEventElapsedTime(&ms[w], h->t_start[j], h->t_stop[j]));
+    }
+    *n = w;
     return SNERG_OK;
 }
 

@@ -112,6 +112,8 @@ def lib():
             "snerg_adam_step": [_P, _P, _P, _P, _P, i64, _P, _P],
             "snerg_bake_cull": [_P, i32, i32, _P, _P, i32, _P, _P, _P, _P, _P, _P],
             "snerg_bake_quantize": [_P, i32, i32, _P, _P, _P, _P, i32, _P, _P, _P, _P, _P],
+            "snerg_timing_enable": [_P, i32],
+            "snerg_timing_read": [_P, _P, i32, _P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -128,7 +130,7 @@ def lib():
 EXPORTED = ["snerg_create", "snerg_destroy", "snerg_status_string", "snerg_last_error", "snerg_packed_size",
             "snerg_pack_grid", "snerg_render", "snerg_render_backward", "snerg_trace_visits",
             "snerg_set_tuning", "snerg_get_tuning", "snerg_autotune", "snerg_loss_mse", "snerg_adam_step",
-            "snerg_bake_cull", "snerg_bake_quantize"]
+            "snerg_bake_cull", "snerg_bake_quantize", "snerg_timing_enable", "snerg_timing_read"]
 
 
 def _check(rc: int, what: str):
@@ -232,6 +234,18 @@ def snerg_adam_step(handle, param, grad, m, v, n, lr, step, beta1=0.9, beta2=0.9
     cfg = snerg_adam(float(lr), float(beta1), float(beta2), float(eps), int(step), 0)
     _check(lib().snerg_adam_step(handle.h, _ptr(param), _ptr(grad), _ptr(m), _ptr(v), int(n), ctypes.byref(cfg),
                                  _stream(stream)), "snerg_adam_step")
+
+
+def snerg_timing_enable(handle, on=True):
+    _check(lib().snerg_timing_enable(handle.h, int(bool(on))), "snerg_timing_enable")
+
+
+def snerg_timing_read(handle, max_n=256):
+    """Render-kernel times (ms) recorded since timing was enabled, oldest first."""
+    buf = (ctypes.c_float * max_n)()
+    n = ctypes.c_int32(0)
+    _check(lib().snerg_timing_read(handle.h, buf, int(max_n), ctypes.byref(n)), "snerg_timing_read")
+    return [float(buf[i]) for i in range(n.value)]
 
 
 def make_bake_opts(tau_alpha=0.005, tau_vis=0.01, sigma_scale=50.0):

@@ -251,3 +251,14 @@ def test_bake_entry_point_validation():
     assert quant(out=None) == S.SNERG_ERR_INVALID_ARG and "NULL" in last_error()
     assert quant(n=0, sg=None, out=None) == S.SNERG_ERR_INVALID_ARG and "handle" in last_error()
     assert quant(o=S.make_bake_opts(sigma_scale=-1.0)) == S.SNERG_ERR_INVALID_ARG
+
+
+def test_timing_entry_point_validation():
+    lib = S.lib()
+    n = ctypes.c_int32(0)
+    buf = (ctypes.c_float * 4)()
+    assert lib.snerg_timing_enable(None, 1) == S.SNERG_ERR_INVALID_ARG and "handle" in last_error()
+    assert lib.snerg_timing_read(None, buf, 4, None) == S.SNERG_ERR_INVALID_ARG
+    assert lib.snerg_timing_read(None, None, 4, ctypes.byref(n)) == S.SNERG_ERR_INVALID_ARG
+    assert lib.snerg_timing_read(None, buf, -1, ctypes.byref(n)) == S.SNERG_ERR_INVALID_ARG
+    assert lib.snerg_timing_read(None, buf, 4, ctypes.byref(n)) == S.SNERG_ERR_INVALID_ARG and "handle" in last_error()

@@ -195,3 +195,27 @@ def test_large1024_all_cameras_one_launch_sampled():
     err, flagged = parity_error(got, oracle_variants(og, mlp, cams, ids=ids))
     say(f"  fp16 max_err={err.max():.3e} near_threshold={flagged} hit_frac={(got[:, 3] > 0).mean():.3f}")
     assert err.max() <= TOL_F16
+
+
+def test_kernel_timing_ring():
+    say("kernel timing: one event pair per render, every launch mode")
+    g, cams, mlp = tiny_case(64, 1)
+    dg = device_grid(g)
+    h = handle()
+    n = sum(c.n_rays for c in cams)
+    out = torch.empty((n, 4), device="cuda")
+    m = S.mlp_tensor(mlp)
+    carr = S.make_cameras(cams)
+    ids = torch.arange(0, n, 3, device="cuda")
+    S.snerg_timing_enable(h, True)
+    for kw in (dict(), dict(persistent=True), dict(persistent=True, graph=True)):
+        S.snerg_render(h, dg.struct(), m, carr, None, n, S.make_opts(**kw), out)
+    S.snerg_render(h, dg.struct(), m, carr, ids, ids.numel(), S.make_opts(), out)
+    ms = S.snerg_timing_read(h)
+    S.snerg_timing_enable(h, False)
+    S.snerg_render(h, dg.struct(), m, carr, None, n, S.make_opts(), out)
+    assert len(ms) == 4 and all(0.0 < t < 1000.0 for t in ms)
+    assert len(S.snerg_timing_read(h)) == 4  # disabled: nothing more recorded
+    S.snerg_timing_enable(h, True)
+    assert S.snerg_timing_read(h) == []
+    S.snerg_timing_enable(h, False)
