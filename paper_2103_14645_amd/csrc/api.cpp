@@ -153,7 +153,7 @@ struct snerg_handle {
     size_t partial_cap = 0;
     float* d_gcv = nullptr;  // per-ray g_C, g_V of the backward pass
     size_t gcv_cap = 0;
-    float* d_tiles = nullptr;  // heavy-first tile order: order [tiles] int32, counts [32], classes [tiles] u8
+    float* d_tiles = nullptr;  // heavy-first tile order: counters [64], order [tiles] int32, classes [tiles] u8
     size_t tiles_cap = 0;      // in floats
     float* d_bake = nullptr;  // baking scratch: per-block max density, visibility words, atlas map
     size_t bake_cap = 0;      // in floats
@@ -293,11 +293,17 @@ int render_impl(snerg_handle* h, const snerg_grid* grid, const float* mlp, const
         return SNERG_OK;
     }
     // heavy-first tile order (scheduling only: every tile's result is unchanged)
-    const size_t order_words = size_t(total_tiles) + 2 * kCostClasses;
+    // layout: counters [64] (fixed place), order [tiles], classes [tiles] bytes
+    const size_t order_words = 64 + size_t(total_tiles);
+    float* const before = h->d_tiles;
     if ((rc = ensure_buffer(&h->d_tiles, &h->tiles_cap, order_words + (size_t(total_tiles) + 3) / 4))) return rc;
-    int32_t* order = reinterpret_cast<int32_t*>(h->d_tiles);
-    int32_t* counts = order + total_tiles;
+    int32_t* counts = reinterpret_cast<int32_t*>(h->d_tiles);
+    int32_t* order = counts + 64;
     uint8_t* cls = reinterpret_cast<uint8_t*>(h->d_tiles + order_words);
+    if (h->d_tiles != before) {
+        // the order kernels leave their counters at zero; a new buffer starts at zero
+        HIP_TRY(launch_fill_i32(counts, 64, 0, s));
+    }
     a.tile_order = order;
     if (!(opts->flags & SNERG_FLAG_PERSISTENT)) {
         a.mode = kModeTiles;

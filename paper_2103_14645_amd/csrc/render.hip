@@ -250,7 +250,7 @@ __global__ __launch_bounds__(256) void k_trace(RenderArgs a) {
 // them in decreasing class.  Pass 1: one lane per tile computes its class
 // and the class histogram.  Pass 2: each workgroup reserves, per class, a
 // range after all tiles of higher classes and writes its tiles there.
-__global__ __launch_bounds__(256) void k_tile_cost(RenderArgs a, uint8_t* __restrict__ cls,
+__global__ __launch_bounds__(64) void k_tile_cost(RenderArgs a, uint8_t* __restrict__ cls,
                                                    int32_t* __restrict__ counts) {
     __shared__ int32_t hist[kCostClasses];
     if (threadIdx.x < kCostClasses) hist[threadIdx.x] = 0;
@@ -275,10 +275,14 @@ __global__ __launch_bounds__(256) void k_tile_cost(RenderArgs a, uint8_t* __rest
     if (threadIdx.x < kCostClasses && hist[threadIdx.x] > 0) atomicAdd(&counts[threadIdx.x], hist[threadIdx.x]);
 }
 
-// counts[0..15]: class sizes; counts[16..31]: per-class cursors (zero).
+// counts[0..15]: class sizes; counts[16..31]: per-class cursors; counts[32]:
+// finished workgroups.  All zero on entry; the last workgroup to finish
+// zeroes them again for the next frame (so no clearing launch is needed,
+// also inside a replayed graph).
 __global__ __launch_bounds__(256) void k_tile_sort(const uint8_t* __restrict__ cls, int32_t* __restrict__ counts,
                                                    int64_t total, int32_t* __restrict__ order) {
     __shared__ int32_t local[kCostClasses], base[kCostClasses];
+    __shared__ bool last;
     if (threadIdx.x < kCostClasses) local[threadIdx.x] = 0;
     __syncthreads();
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -293,16 +297,26 @@ __global__ __launch_bounds__(256) void k_tile_sort(const uint8_t* __restrict__ c
     }
     __syncthreads();
     if (c >= 0) order[base[c] + pos] = int32_t(t);
+    if (threadIdx.x == 0) {
+        __threadfence();  // this workgroup's reads of counts happen before its ticket
+        last = atomicAdd(&counts[2 * kCostClasses], 1) == int32_t(gridDim.x) - 1;
+    }
+    __syncthreads();
+    if (last && threadIdx.x <= 2 * kCostClasses) {
+        __threadfence();
+        atomicExch(&counts[threadIdx.x], 0);
+    }
 }
 
 hipError_t launch_tile_order(const RenderArgs& a, uint8_t* cls, int32_t* counts, int32_t* order, hipStream_t s) {
     if (a.total_tiles <= 0) return hipSuccess;
-    hipError_t e = launch_fill_i32(counts, 2 * kCostClasses, 0, s);
+    // one wavefront per workgroup: the walk is a latency chain, so spread it over many CUs
+    const unsigned cblocks = unsigned((a.total_tiles + 63) / 64);
+    const size_t lds = size_t(a.grid.n_words) * sizeof(uint2);
+    hipLaunchKernelGGL(k_tile_cost, dim3(cblocks), dim3(64), lds, s, a, cls, counts);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const unsigned blocks = unsigned((a.total_tiles + 255) / 256);
-    const size_t lds = size_t(a.grid.n_words) * sizeof(uint2);
-    hipLaunchKernelGGL(k_tile_cost, dim3(blocks), dim3(256), lds, s, a, cls, counts);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_tile_sort, dim3(blocks), dim3(256), 0, s, cls, counts, a.total_tiles, order);
     return hipGetLastError();
 }
