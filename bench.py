@@ -44,7 +44,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-RENDER_SOURCES = ("render.hip", "march.h", "mlp.h", "snerg_dev.h", "snerg_launch.h")
+RENDER_SOURCES = ("render.hip", "march.h", "mlp.h", "snerg_dev.h", "snerg_launch.h", "api.cpp")  # kernel and its launch order
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_render_plain512_traffic.md")
 COPY_BYTES = 1 << 30
 
