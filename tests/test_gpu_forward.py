@@ -219,3 +219,68 @@ def test_kernel_timing_ring():
     S.snerg_timing_enable(h, True)
     assert S.snerg_timing_read(h) == []
     S.snerg_timing_enable(h, False)
+
+
+def _cluster_grid(N, B, radius, seed):
+    """Occupied macroblocks in a cube of (2 radius)^3 blocks around the centre
+    (random bytes, a quarter of the densities zero), atlas ids permuted."""
+    rng = np.random.default_rng(seed)
+    G = N // B
+    lo, hi = max(0, G // 2 - radius), min(G, G // 2 + radius)
+    bz, by, bx = np.meshgrid(np.arange(lo, hi), np.arange(lo, hi), np.arange(lo, hi), indexing="ij")
+    lin = ((bz * G + by) * G + bx).reshape(-1)
+    n = lin.size
+    ind = np.full(G ** 3, -1, np.int32)
+    ind[lin] = rng.permutation(n).astype(np.int32)
+    dens = rng.integers(0, 256, (n, B, B, B), dtype=np.uint8)
+    dens[rng.random(dens.shape) < 0.25] = 0
+    rgb = rng.integers(0, 256, (n, B, B, B, 3), dtype=np.uint8)
+    feat = rng.integers(0, 256, (n, B, B, B, 4), dtype=np.uint8)
+    return W.Grid(N, B, ind, dens, rgb, feat)
+
+
+def _axis_camera(N, yv, zv):
+    # one ray along +x through the point (yv, zv) in voxel units (may sit on a face)
+    y = yv * 2.0 / N - 1.0
+    z = zv * 2.0 / N - 1.0
+    fwd, up = np.array([1.0, 0.0, 0.0]), np.array([0.0, 0.0, 1.0])
+    return W.Camera(np.array([-2.5, y, z]), fwd, np.cross(fwd, up), up, 1, 1, 1.0)
+
+
+@pytest.mark.parametrize("N,B,radius,fov", [(4096, 64, 1, 3.0), (2, 2, 1, 25.0), (96, 32, 2, 25.0)])
+def test_extreme_grid_shapes(N, B, radius, fov):
+    # N = 4096, B = 64: the largest grid whose occupancy table (64^3 blocks,
+    # 64 KB) fits in LDS, and lattice coordinates up to 2^28; N = 2: a single
+    # macroblock of 8 voxels; G = 3: an odd block count.  Cameras outside and
+    # inside the grid, and axis-aligned rays through voxel centres and exactly
+    # along macroblock faces.
+    say(f"extreme shape N={N} B={B}")
+    g = _cluster_grid(N, B, radius, seed=N + B)
+    mid = N / 2.0
+    cams = [W.orbit_camera(48, 40, fov_deg=fov, seed=1),
+            W.look_at((0.05, -0.1, 0.02), 32, 24, 90.0, target=(0.9, 0.3, -0.2)),   # eye inside the grid
+            _axis_camera(N, mid + 0.5, mid + 0.5), _axis_camera(N, mid, mid), _axis_camera(N, mid - B, mid + 0.25)]
+    mlp = W.mlp_weights(3)
+    n = sum(c.n_rays for c in cams)
+    ids = None
+    dg = device_grid(g)
+    gpu = gpu_render(dg, mlp, cams, ids=ids)
+    og = O.OracleGrid(g)
+    err, flagged = parity_error(gpu, oracle_variants(og, mlp, cams, ids=ids))
+    say(f"  rays={len(err)} max_err={err.max():.3e} near_threshold={flagged} hit={np.mean(gpu[:, 3] > 0):.2f}")
+    assert err.max() <= TOL_F32
+    assert np.mean(gpu[:, 3] > 0) > 0.05
+    # visit lists bit-exact without early stop
+    nr = n
+    idt = torch.arange(n, device="cuda")
+    visits = torch.full((nr, 32), -7, dtype=torch.int32, device="cuda")
+    counts = torch.empty(nr, dtype=torch.int32, device="cuda")
+    S.snerg_trace_visits(handle(), dg.struct(), S.make_cameras(cams), idt, nr, S.make_opts(early_stop=False),
+                         32, visits, counts)
+    torch.cuda.synchronize()
+    ovis, ocnt = O.trace_visits(og, cams, ray_ids=ids, early_stop=False, max_visits=32)
+    assert np.array_equal(counts.cpu().numpy(), ocnt)
+    gv = visits.cpu().numpy()
+    for r in range(nr):
+        k = min(int(ocnt[r]), 32)
+        assert np.array_equal(gv[r, :k], ovis[r, :k]), r
