@@ -359,7 +359,8 @@ def leg_finetune(args, torch, S, W):
     gen = torch.Generator(device="cuda")
     gen.manual_seed(3)
     order = torch.randperm(n, device="cuda", generator=gen)
-    batches = [order[i * mb:(i + 1) * mb] for i in range(n // mb)]
+    # minibatches drawn at random, each handed over in ray-id order (as MlpFineTuner.epoch does)
+    batches = [order[i * mb:(i + 1) * mb].sort().values for i in range(n // mb)]
     it = [0]
     losses = []
 
