@@ -292,17 +292,23 @@ int render_impl(snerg_handle* h, const snerg_grid* grid, const float* mlp, const
         HIP_TRY(timing_end(h, s));
         return SNERG_OK;
     }
-    // heavy-first tile order (scheduling only: every tile's result is unchanged)
+    // heavy-first tile order (scheduling only: every tile's result is unchanged;
+    // int32 entries, so frames of more than 2^31 - 1 tiles keep image order)
     // layout: counters [64] (fixed place), order [tiles], classes [tiles] bytes
-    const size_t order_words = 64 + size_t(total_tiles);
-    float* const before = h->d_tiles;
-    if ((rc = ensure_buffer(&h->d_tiles, &h->tiles_cap, order_words + (size_t(total_tiles) + 3) / 4))) return rc;
-    int32_t* counts = reinterpret_cast<int32_t*>(h->d_tiles);
-    int32_t* order = counts + 64;
-    uint8_t* cls = reinterpret_cast<uint8_t*>(h->d_tiles + order_words);
-    if (h->d_tiles != before) {
-        // the order kernels leave their counters at zero; a new buffer starts at zero
-        HIP_TRY(launch_fill_i32(counts, 64, 0, s));
+    int32_t* counts = nullptr;
+    int32_t* order = nullptr;
+    uint8_t* cls = nullptr;
+    if (total_tiles <= int64_t(INT32_MAX)) {
+        const size_t order_words = 64 + size_t(total_tiles);
+        float* const before = h->d_tiles;
+        if ((rc = ensure_buffer(&h->d_tiles, &h->tiles_cap, order_words + (size_t(total_tiles) + 3) / 4))) return rc;
+        counts = reinterpret_cast<int32_t*>(h->d_tiles);
+        order = counts + 64;
+        cls = reinterpret_cast<uint8_t*>(h->d_tiles + order_words);
+        if (h->d_tiles != before) {
+            // the order kernels leave their counters at zero; a new buffer starts at zero
+            HIP_TRY(launch_fill_i32(counts, 64, 0, s));
+        }
     }
     a.tile_order = order;
     if (!(opts->flags & SNERG_FLAG_PERSISTENT)) {

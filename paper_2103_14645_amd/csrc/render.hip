@@ -309,7 +309,7 @@ __global__ __launch_bounds__(256) void k_tile_sort(const uint8_t* __restrict__ c
 }
 
 hipError_t launch_tile_order(const RenderArgs& a, uint8_t* cls, int32_t* counts, int32_t* order, hipStream_t s) {
-    if (a.total_tiles <= 0) return hipSuccess;
+    if (a.total_tiles <= 0 || !order) return hipSuccess;
     // one wavefront per workgroup: the walk is a latency chain, so spread it over many CUs
     const unsigned cblocks = unsigned((a.total_tiles + 63) / 64);
     const size_t lds = size_t(a.grid.n_words) * sizeof(uint2);

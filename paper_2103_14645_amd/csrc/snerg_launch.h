@@ -108,7 +108,7 @@ hipError_t launch_render(const RenderArgs& a, int vt, int mlp_mode, int waves_pe
 hipError_t launch_trace(const RenderArgs& a, int vt, hipStream_t s);
 // Heavy-first tile order for a tiled or persistent render: `cls` [total_tiles]
 // and `counts` [33] are scratch (counts zero on entry, left zero on exit),
-// `order` [total_tiles] receives the order.
+// `order` [total_tiles] receives the order (null: nothing to do).
 constexpr int kCostClasses = 16;
 hipError_t launch_tile_order(const RenderArgs& a, uint8_t* cls, int32_t* counts, int32_t* order, hipStream_t s);
 hipError_t launch_backward(const BackwardArgs& a, int n_groups, hipStream_t s);
