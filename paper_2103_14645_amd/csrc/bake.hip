@@ -93,8 +93,14 @@ struct BakeVisArgs {
 // Samples loaded ahead of the sequential prefix sum.
 constexpr int kVisAhead = 4;
 
-// IDX32: N^3 < 2^32, voxel indices in 32-bit arithmetic.
-template <bool IDX32>
+// Voxel index arithmetic of the march: kIdx64 for any N, kIdx32 when
+// N^3 < 2^32 (24-bit multiplies), kIdxPow2 when N is a power of two up to
+// 1024 (bit fields: the voxel index is vx | vy << lg | vz << 2 lg, and the
+// macroblock is that index with the low logB bits of each field masked off,
+// one AND per sample).
+enum { kIdx64 = 0, kIdx32 = 1, kIdxPow2 = 2 };
+
+template <int IDX>
 __global__ __launch_bounds__(256) void k_bake_visibility(BakeVisArgs a) {
     // Per-workgroup cache of bounds on the blocks' minima: 256 slots indexed
     // by the low 8 bits of the block index, each one 32-bit word (read and
@@ -130,6 +136,10 @@ __global__ __launch_bounds__(256) void k_bake_visibility(BakeVisArgs a) {
     const int32_t n = int32_t(khi - klo + 1);
     const uint32_t N = uint32_t(a.N), G = uint32_t(a.G);
     const int bs = 16 + a.logB;
+    int lg = 0;
+    while ((1 << lg) < a.N) ++lg;
+    const uint32_t fmask = (G - 1) << a.logB;  // block bits of one coordinate field
+    const uint32_t bmask = fmask | (fmask << lg) | (fmask << (2 * lg));
     const double thr = a.sum_thr;
     double sum = 0.0;
     uint32_t prev = 0xffffffffu;
@@ -149,15 +159,21 @@ __global__ __launch_bounds__(256) void k_bake_visibility(BakeVisArgs a) {
 #pragma unroll
                 for (int q = 0; q < 3; ++q) Q[q] += uint32_t(s[q]) & m;
             }
-            if (IDX32) {  // every factor and partial sum below 2^24
-                const uint32_t v = __umul24(__umul24(Q[2] >> 16, N) + (Q[1] >> 16), N) + (Q[0] >> 16);
+            if (IDX == kIdxPow2) {
+                const uint32_t v = (Q[0] >> 16) | ((Q[1] >> 16) << lg) | ((Q[2] >> 16) << (2 * lg));
                 sv[u] = a.sigma[v];
+                bk[u] = v & bmask;
             } else {
-                const uint64_t v = (uint64_t(Q[2] >> 16) * N + (Q[1] >> 16)) * N + (Q[0] >> 16);
-                sv[u] = a.sigma[v];
+                if (IDX == kIdx32) {  // every factor and partial sum below 2^24
+                    const uint32_t v = __umul24(__umul24(Q[2] >> 16, N) + (Q[1] >> 16), N) + (Q[0] >> 16);
+                    sv[u] = a.sigma[v];
+                } else {
+                    const uint64_t v = (uint64_t(Q[2] >> 16) * N + (Q[1] >> 16)) * N + (Q[0] >> 16);
+                    sv[u] = a.sigma[v];
+                }
+                // macroblock coordinates packed 8 bits each (G <= 64)
+                bk[u] = (Q[0] >> bs) | ((Q[1] >> bs) << 8) | ((Q[2] >> bs) << 16);
             }
-            // macroblock coordinates packed 8 bits each (G <= 64)
-            bk[u] = (Q[0] >> bs) | ((Q[1] >> bs) << 8) | ((Q[2] >> bs) << 16);
         }
 #pragma unroll
         for (int u = 0; u < kVisAhead; ++u) {
@@ -168,7 +184,17 @@ __global__ __launch_bounds__(256) void k_bake_visibility(BakeVisArgs a) {
                     prev = bk[u];
                     if (sum <= thr) {
                         const uint64_t bits = uint64_t(__double_as_longlong(sum));
-                        const uint32_t lin = __umul24(__umul24(bk[u] >> 16, G) + ((bk[u] >> 8) & 0xff), G) + (bk[u] & 0xff);
+                        uint32_t bx, by, bz;
+                        if (IDX == kIdxPow2) {
+                            bx = (bk[u] >> a.logB) & (G - 1);
+                            by = (bk[u] >> (lg + a.logB)) & (G - 1);
+                            bz = bk[u] >> (2 * lg + a.logB);
+                        } else {
+                            bx = bk[u] & 0xff;
+                            by = (bk[u] >> 8) & 0xff;
+                            bz = bk[u] >> 16;
+                        }
+                        const uint32_t lin = __umul24(__umul24(bz, G) + by, G) + bx;
                         const uint32_t key = vcache[lin & 255];
                         if ((key >> 22) != (lin >> 8) || double(__uint_as_float((key & 0x3fffffu) << 10)) > sum) {
                             uint64_t* w = a.depth_bits + lin;
@@ -372,10 +398,12 @@ hipError_t launch_bake_cull(const BakeCullPlan& p, hipStream_t s) {
         v.sum_thr = p.sum_thr;
         v.depth_bits = p.depth_bits;
         const unsigned blocks = unsigned((p.total_tiles + 3) / 4);
-        if (int64_t(p.N) * p.N * p.N <= int64_t(0xffffffffu))
-            hipLaunchKernelGGL(k_bake_visibility<true>, dim3(blocks), dim3(256), 0, s, v);
+        if ((p.N & (p.N - 1)) == 0 && p.N <= 1024)
+            hipLaunchKernelGGL(k_bake_visibility<kIdxPow2>, dim3(blocks), dim3(256), 0, s, v);
+        else if (int64_t(p.N) * p.N * p.N <= int64_t(0xffffffffu))
+            hipLaunchKernelGGL(k_bake_visibility<kIdx32>, dim3(blocks), dim3(256), 0, s, v);
         else
-            hipLaunchKernelGGL(k_bake_visibility<false>, dim3(blocks), dim3(256), 0, s, v);
+            hipLaunchKernelGGL(k_bake_visibility<kIdx64>, dim3(blocks), dim3(256), 0, s, v);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     BakeCompactArgs c;
