@@ -343,7 +343,9 @@ def leg_finetune(args, torch, S, W):
     """Fine-tuning of the deferred network on the fixed 512^3 uint8 SNeRG
     (Section 5.5): 65,536-ray minibatches over the 8 adjoint views, targets
     rendered with the original weights, training from perturbed weights;
-    each step is render + squared error + MLP backward + Adam."""
+    each step is render + squared error + MLP backward + Adam.  Two ways of
+    drawing the minibatches: independent pixels (in ray-id order) and whole
+    8x8 patches."""
     from paper_2103_14645_amd import finetune as F
     cfg = W.config("adjoint512")
     g, cams, mlp = cfg["grid"], cfg["cams"], cfg["mlp"]
@@ -353,28 +355,40 @@ def leg_finetune(args, torch, S, W):
     target = torch.empty((n, 4), device="cuda")
     S.snerg_render(h, dg.struct(), S.mlp_tensor(mlp), S.make_cameras(cams), None, n, S.make_opts(), target)
     start, _ = W.perturbed(mlp, g, rel=0.3)
-    w = S.mlp_tensor(start)
     mb = 65536
-    ft = F.MlpFineTuner(h, dg.struct(), w, cams, target, lr=3e-4, max_batch=mb)
     gen = torch.Generator(device="cuda")
     gen.manual_seed(3)
     order = torch.randperm(n, device="cuda", generator=gen)
-    # minibatches drawn at random, each handed over in ray-id order (as MlpFineTuner.epoch does)
-    batches = [order[i * mb:(i + 1) * mb].sort().values for i in range(n // mb)]
-    it = [0]
-    losses = []
+    cgen = torch.Generator()
+    cgen.manual_seed(3)
+    sampling = {
+        # rays drawn independently, each minibatch handed over in ray-id order (MlpFineTuner.epoch)
+        "pixels": [order[i * mb:(i + 1) * mb].sort().values for i in range(n // mb)],
+        # whole 8x8 patches in random order (MlpFineTuner.epoch(patches=True))
+        "patches": None,
+    }
+    res = dict(minibatch=mb, rays_total=n)
+    for kind in ("pixels", "patches"):
+        w = S.mlp_tensor(start)
+        ft = F.MlpFineTuner(h, dg.struct(), w, cams, target, lr=3e-4, max_batch=mb)
+        if kind == "patches":
+            po = ft.patch_order(cgen)
+            sampling[kind] = [po[i * mb:(i + 1) * mb] for i in range(n // mb)]
+        batches = sampling[kind]
+        it = [0]
+        losses = []
 
-    def step():
-        losses.append(ft.step(batches[it[0] % len(batches)]))
-        it[0] += 1
+        def step():
+            losses.append(ft.step(batches[it[0] % len(batches)]))
+            it[0] += 1
 
-    steps = max(4, args.steps)
-    ms = time_launches(step, steps, 2, torch)
-    ls = [float(x.item()) for x in losses]
-    res = dict(ms_step=ms, steps_per_s=1000.0 / ms, mrays=mb / ms / 1e3, minibatch=mb, rays_total=n,
-               loss_first=ls[0], loss_last=ls[-1], steps_run=len(ls))
-    log(f"finetune: {ms:.3f} ms/step ({res['steps_per_s']:.0f} steps/s, {res['mrays']:.1f} Mrays/s), "
-        f"loss {ls[0]:.5f} -> {ls[-1]:.5f} over {len(ls)} steps")
+        steps = max(4, args.steps)
+        ms = time_launches(step, steps, 2, torch)
+        ls = [float(x.item()) for x in losses]
+        res[kind] = dict(ms_step=ms, steps_per_s=1000.0 / ms, mrays=mb / ms / 1e3, loss_first=ls[0],
+                         loss_last=ls[-1], steps_run=len(ls))
+        log(f"finetune ({kind}): {ms:.3f} ms/step ({1000.0 / ms:.0f} steps/s, {mb / ms / 1e3:.1f} Mrays/s), "
+            f"loss {ls[0]:.5f} -> {ls[-1]:.5f} over {len(ls)} steps")
     return res
 
 
@@ -554,7 +568,8 @@ def main():
                                        for k, v in extra["nondeferred"].items()}
     if "finetune" in extra:
         f = extra["finetune"]
-        legs_out["finetune_mlp_512"] = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in f.items()}
+        legs_out["finetune_mlp_512"] = {k: ({kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                                            if isinstance(v, dict) else v) for k, v in f.items()}
     if "bake" in extra:
         legs_out["bake_512"] = {k: (round(v, 5) if isinstance(v, float) else v) for k, v in extra["bake"].items()}
     if "copy" in extra:

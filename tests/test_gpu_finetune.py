@@ -125,3 +125,20 @@ def test_finetuning_lowers_the_loss_on_the_gpu():
         losses += [float(x.item()) for x in ft.epoch(512, gen)]
     say(f"  first {np.mean(losses[:3]):.5f} last {np.mean(losses[-3:]):.5f} over {len(losses)} steps")
     assert np.mean(losses[-3:]) < 0.7 * np.mean(losses[:3])
+
+
+def test_finetuning_with_patch_minibatches_lowers_the_loss():
+    say("fine-tuning: six epochs of 512-ray minibatches of whole 8x8 patches")
+    g, cams, mlp, start = _case(seed=9)
+    og = O.OracleGrid(g, values=tuple(np.asarray(a, np.float64) / 255.0 for a in (g.dens, g.rgb, g.feat)))
+    target = torch.from_numpy(O.render(og, mlp, cams)["rgba"].astype(np.float32)).cuda()
+    dg = device_grid(g)
+    w = S.mlp_tensor(start)
+    ft = F.MlpFineTuner(handle(), dg.struct(), w, cams, target, lr=3e-3, max_batch=512)
+    gen = torch.Generator()
+    gen.manual_seed(3)
+    losses = []
+    for _ in range(6):
+        losses += [float(x.item()) for x in ft.epoch(512, gen, patches=True)]
+    say(f"  first {np.mean(losses[:3]):.5f} last {np.mean(losses[-3:]):.5f} over {len(losses)} steps")
+    assert np.mean(losses[-3:]) < 0.7 * np.mean(losses[:3])
