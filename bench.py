@@ -246,7 +246,8 @@ def leg_adjoint(args, torch, S, W, O):
 def leg_large(args, torch, S, W, O):
     """64 x 1920x1080 forward in one persistent graph launch (FP16 MLP), then
     forward + backward on random 65,536-ray minibatches over all 64 views
-    (FP16 MLP forward and backward, float32 shadow of the grid)."""
+    (FP16 MLP forward and backward, float32 shadow of the grid): independent
+    pixels, and whole 8x8 patches."""
     from paper_2103_14645_amd import autograd as A
     cfg = W.config("large1024")
     g, cams, mlp = cfg["grid"], cfg["cams"], cfg["mlp"]
@@ -278,7 +279,7 @@ def leg_large(args, torch, S, W, O):
     feat = torch.from_numpy(g.feat).cuda().float().div_(255.0)
     r.pack(dens, rgb, feat)
     sgrid = r.struct()
-    bopts = S.make_opts(fp16=True)
+    bo = [S.make_opts(fp16=True)]
     mb = 65536
     gen = torch.Generator(device="cuda")
     gen.manual_seed(3)
@@ -293,21 +294,38 @@ def leg_large(args, torch, S, W, O):
     def train_step():
         b = batches[it[0] % len(batches)]
         it[0] += 1
-        S.snerg_render(h, sgrid, m, carr, b, mb, bopts, bout, aux)
-        S.snerg_render_backward(h, sgrid, m, carr, b, mb, bopts, aux, gout, gm, gd, gr, gf)
+        S.snerg_render(h, sgrid, m, carr, b, mb, bo[0], bout, aux)
+        S.snerg_render_backward(h, sgrid, m, carr, b, mb, bo[0], aux, gout, gm, gd, gr, gf)
 
     def fwd_only():
         b = batches[it[0] % len(batches)]
         it[0] += 1
-        S.snerg_render(h, sgrid, m, carr, b, mb, bopts, bout, aux)
+        S.snerg_render(h, sgrid, m, carr, b, mb, bo[0], bout, aux)
 
     ms_step = time_launches(train_step, 8, 2, torch)
     ms_f = time_launches(fwd_only, 8, 2, torch)
     ms_b = max(ms_step - ms_f, 1e-6)
+    # the same with minibatches of 1,024 whole 8x8 patches drawn across the 64 views
+    tx, ty = cams[0].W // 8, cams[0].H // 8
+    tiles = torch.randperm(len(cams) * tx * ty, device="cuda", generator=gen)[: 4 * (mb // 64)].view(4, -1)
+    lane = torch.arange(64, device="cuda")
+    def patch_ids(t):
+        c, r = t // (tx * ty), t % (tx * ty)
+        py = (r // tx)[:, None] * 8 + lane[None, :] // 8
+        px = (r % tx)[:, None] * 8 + lane[None, :] % 8
+        return (c[:, None] * (cams[0].W * cams[0].H) + py * cams[0].W + px).reshape(-1)
+    batches = [patch_ids(t) for t in tiles]
+    bo[0] = S.make_opts(fp16=True, patch_rays=True)  # aligned groups of 64 neighbouring rays
+    it[0] = 0
+    ms_step_p = time_launches(train_step, 8, 2, torch)
+    ms_f_p = time_launches(fwd_only, 8, 2, torch)
     res = dict(ms=ms, rays=n, mrays=n / ms / 1e3, max_abs_err=err, tuning=list(best), mb=mb, cpu_mrays=cpu_mrays,
-               ms_train_step=ms_step, ms_mb_fwd=ms_f, bwd_mrays=mb / ms_b / 1e3)
+               ms_train_step=ms_step, ms_mb_fwd=ms_f, bwd_mrays=mb / ms_b / 1e3,
+               ms_train_step_patches=ms_step_p, ms_mb_fwd_patches=ms_f_p,
+               bwd_mrays_patches=mb / max(ms_step_p - ms_f_p, 1e-6) / 1e3)
     log(f"large1024: {ms:.1f} ms/launch, {res['mrays']:.1f} Mrays/s, fp16 err {err:.2e}; minibatch fwd+bwd "
-        f"{ms_step:.2f} ms (bwd {res['bwd_mrays']:.1f} Mrays/s)")
+        f"{ms_step:.2f} ms (bwd {res['bwd_mrays']:.1f} Mrays/s); as 8x8 patches {ms_step_p:.2f} ms "
+        f"(bwd {res['bwd_mrays_patches']:.1f} Mrays/s)")
     return res
 
 
@@ -562,7 +580,9 @@ def main():
                                   "max_abs_err_vs_oracle": b["max_abs_err"], "rays": b["rays"],
                                   "tuning": b["tuning"], "minibatch": b["mb"],
                                   "ms_minibatch_fwd_bwd": round(b["ms_train_step"], 4),
-                                  "bwd_mrays": round(b["bwd_mrays"], 3), "cpu_oracle_mrays": round(b["cpu_mrays"], 4)}
+                                  "bwd_mrays": round(b["bwd_mrays"], 3), "cpu_oracle_mrays": round(b["cpu_mrays"], 4),
+                                  "ms_minibatch_fwd_bwd_patches": round(b["ms_train_step_patches"], 4),
+                                  "bwd_mrays_patches": round(b["bwd_mrays_patches"], 3)}
     if "nondeferred" in extra:
         legs_out["nondeferred_512"] = {k: {kk: round(vv, 5) for kk, vv in v.items()}
                                        for k, v in extra["nondeferred"].items()}

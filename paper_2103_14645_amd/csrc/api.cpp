@@ -91,7 +91,8 @@ int check_opts(const snerg_opts* o) {
         if (!std::isfinite(o->bg[a])) return fail(SNERG_ERR_INVALID_ARG, "opts->bg must be finite");
     if (!std::isfinite(o->t_stop) || o->t_stop < 0.0f) return fail(SNERG_ERR_INVALID_ARG, "opts->t_stop must be finite and >= 0");
     const uint32_t known = SNERG_FLAG_MLP_FP16 | SNERG_FLAG_PERSISTENT | SNERG_FLAG_GRAPH | SNERG_FLAG_MLP_GRAD_ONLY |
-                           SNERG_FLAG_NN_GATE | SNERG_FLAG_UNPREMULTIPLY | SNERG_FLAG_PER_SAMPLE_MLP;
+                           SNERG_FLAG_NN_GATE | SNERG_FLAG_UNPREMULTIPLY | SNERG_FLAG_PER_SAMPLE_MLP |
+                           SNERG_FLAG_PATCH_RAYS;
     if (o->flags & ~known) return fail(SNERG_ERR_UNSUPPORTED, "unknown opts->flags bits");
     return SNERG_OK;
 }
@@ -554,6 +555,7 @@ int snerg_render_backward(snerg_handle* h, const snerg_grid* grid, const float* 
     a.tile_w = h->tuning.tile_w;
     a.tile_h = h->tuning.tile_h;
     a.mlp_only = mlp_only ? 1 : 0;
+    a.patch_rays = (opts->flags & SNERG_FLAG_PATCH_RAYS) ? 1 : 0;
     HIP_TRY(launch_backward(a, n_groups, s));
     if (mlp_mode != kMlpOff) HIP_TRY(launch_reduce_mlp(h->d_partial, rows, grad_mlp, s));
     return SNERG_OK;

@@ -678,7 +678,7 @@ hipError_t launch_backward(const BackwardArgs& a, int n_groups, hipStream_t s) {
     if (a.mlp_only) return hipSuccess;
     // aggregation keys are int32 voxel indices
     const int64_t n_vox = int64_t(a.grid.n_blocks) * a.grid.B * a.grid.B * a.grid.B;
-    const bool agg = !a.ray_ids && n_vox < (int64_t(1) << 31);
+    const bool agg = (!a.ray_ids || a.patch_rays) && n_vox < (int64_t(1) << 31);
     const size_t lds = size_t(a.grid.n_words) * sizeof(uint2) + (agg ? size_t(kAggWaves) * kAggWords * 4 : 0);
     const int64_t waves = a.ray_ids ? (a.n_rays + 63) / 64 : a.total_tiles;
     const unsigned blocks = unsigned((waves + kAggWaves - 1) / kAggWaves);

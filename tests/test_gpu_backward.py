@@ -8,6 +8,7 @@ import torch
 import oracle as O
 import workloads as W
 from paper_2103_14645_amd import autograd as A
+from paper_2103_14645_amd import finetune as F
 from paper_2103_14645_amd import snerg as S
 from tests.gpu_helpers import handle, say
 
@@ -80,6 +81,38 @@ def test_backward_matches_oracle_gradient(n_occ, seed, early, mlp_on, subset):
     compare("feat", gf, of)
     ref = O.render(og, mlp, cams, ray_ids=ids, early_stop=early, mlp_on=mlp_on)["rgba"]
     assert np.abs(out - ref).max() <= 1e-4
+
+
+@pytest.mark.parametrize("layout", ["patches", "scattered"])
+def test_patch_ray_lists_match_oracle_gradient(layout):
+    # SNERG_FLAG_PATCH_RAYS: ray lists aggregated per wavefront in LDS; exact
+    # up to summation order for any list, patch-shaped (as the fine-tuning
+    # patch sampler draws them, ragged patches included) or not
+    say(f"backward with SNERG_FLAG_PATCH_RAYS, {layout} list")
+    seed = 8
+    g = W.tiny_grid(n_occupied=200, seed=seed)
+    vals = shadow_values(g, seed)
+    mlp = W.mlp_weights(seed + 1)
+    cams = [W.orbit_camera(48, 40, seed=seed + 2), W.orbit_camera(21, 35, seed=seed + 3)]
+    n = sum(c.n_rays for c in cams)
+    rng = np.random.default_rng(seed)
+    if layout == "patches":
+        class _C:
+            cam_list, mlp = cams, torch.zeros(1)
+        gen = torch.Generator()
+        gen.manual_seed(seed)
+        ids = F.MlpFineTuner.patch_order(_C(), gen).numpy()[: n // 2]
+    else:
+        ids = rng.permutation(n)[: n // 2]
+    og = O.OracleGrid(g, values=vals)
+    ids = stable_ids(og, mlp, cams, ids)
+    g_rgba = rng.normal(size=(len(ids), 4)) / len(ids)
+    gm, gd, gr, gf, out = run_backward(g, vals, mlp, cams, g_rgba, ids=ids, patch_rays=True)
+    om, od, orr, of = O.render_grad(og, mlp, cams, g_rgba, ray_ids=ids)
+    compare("mlp", gm, om)
+    compare("dens", gd, od)
+    compare("rgb", gr, orr)
+    compare("feat", gf, of)
 
 
 def test_mse_step_reduces_loss():
