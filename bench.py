@@ -44,6 +44,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP16_PEAK_TFLOPS = 2500.0  # dense FP16 MFMA
+MLP_FLOP = 2 * (34 * 16 + 16 * 16 + 16 * 3)
 RENDER_SOURCES = ("render.hip", "march.h", "mlp.h", "snerg_dev.h", "snerg_launch.h", "api.cpp")  # kernel and its launch order
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_render_plain512_traffic.md")
 COPY_BYTES = 1 << 30
@@ -200,9 +202,14 @@ def leg_batched(args, torch, S, W, O):
     ids = np.sort(np.random.default_rng(3).choice(n, 4096, replace=False))
     ref, cpu_mrays = oracle_rate(O, O.OracleGrid(g), mlp, cams, ids, args.cpu_threads)
     err = float(np.abs(frame[ids] - ref).max())
+    # the deferred network: 1,696 FLOP per ray (34x16 + 16x16 + 16x3 multiply-adds); on MFMA tiles
+    # 20 v_mfma_f32_16x16x16_f16 of 8,192 FLOP per 64 rays (K and N padded) are executed
+    mlp_tflops = n * MLP_FLOP / (ms * 1e-3) / 1e12
     res = dict(ms=ms, rays=n, mrays=n / ms / 1e3, max_abs_err=err, err_sample=len(ids), tuning=list(best),
-               cpu_mrays=cpu_mrays)
-    log(f"batched1024: {ms:.3f} ms/batch, {res['mrays']:.1f} Mrays/s, fp16 max-abs err {err:.2e}")
+               cpu_mrays=cpu_mrays, mlp_tflops=mlp_tflops, mfma_frac=mlp_tflops / FP16_PEAK_TFLOPS,
+               mfma_tflops_executed=n / 64 * 20 * 8192 / (ms * 1e-3) / 1e12)
+    log(f"batched1024: {ms:.3f} ms/batch, {res['mrays']:.1f} Mrays/s, fp16 max-abs err {err:.2e}; MLP "
+        f"{mlp_tflops:.2f} TFLOP/s = {100 * res['mfma_frac']:.3f}% of the FP16 MFMA peak")
     return res
 
 
@@ -238,8 +245,22 @@ def leg_adjoint(args, torch, S, W, O):
     steps = max(2, args.steps // 4)
     ms_f = time_launches(fwd, steps, 1, torch)
     ms_b = time_launches(bwd, steps, 1, torch)
-    res = dict(ms_fwd=ms_f, ms_bwd=ms_b, rays=n, fwd_mrays=n / ms_f / 1e3, bwd_mrays=n / ms_b / 1e3)
-    log(f"adjoint512: fwd {ms_f:.3f} ms, bwd {ms_b:.3f} ms -> {res['bwd_mrays']:.1f} bwd Mrays/s")
+    # Algorithmic bytes on the float32 shadow (same traversal as the uint8 grid: the zero
+    # pattern is the same).  Forward: 4 B per macroblock, 1 B per in-block sample, 8 corners x
+    # 32 B per composited sample, 16 B RGBA + 32 B aux per ray.  Backward: the re-march reads
+    # the same, plus aux, dL/dRGBA and the per-ray dL/d(C, V) (32 + 16 + 32 B per ray); the
+    # gradient scatter is not counted, so this is a lower bound.
+    dgu = S.DeviceGrid(h, g.N, g.B, g.indirection, g.dens, g.rgb, g.feat)
+    cnt = frame_counters(S, h, dgu, cams)
+    del dgu
+    march = 4 * cnt["blocks"] + cnt["inblock"] + 256 * cnt["active"]
+    fwd_bytes = march + 48 * cnt["rays"]
+    bwd_bytes = march + 80 * cnt["rays"]
+    res = dict(ms_fwd=ms_f, ms_bwd=ms_b, rays=n, fwd_mrays=n / ms_f / 1e3, bwd_mrays=n / ms_b / 1e3,
+               fwd_alg_gbs=fwd_bytes / (ms_f * 1e-3) / 1e9, bwd_alg_gbs=bwd_bytes / (ms_b * 1e-3) / 1e9,
+               counters=cnt)
+    log(f"adjoint512: fwd {ms_f:.3f} ms, bwd {ms_b:.3f} ms -> {res['bwd_mrays']:.1f} bwd Mrays/s; algorithmic "
+        f"{res['fwd_alg_gbs']:.0f} / {res['bwd_alg_gbs']:.0f} GB/s (fwd / bwd, bwd a lower bound)")
     return res
 
 
@@ -567,12 +588,23 @@ def main():
                                          "fps_800x800_equiv": round(b["mrays"] / 0.64, 2),
                                          "max_abs_err_vs_oracle": b["max_abs_err"], "err_sample": b["err_sample"],
                                          "rays": b["rays"], "tuning": b["tuning"],
-                                         "cpu_oracle_mrays": round(b["cpu_mrays"], 4)}
+                                         "cpu_oracle_mrays": round(b["cpu_mrays"], 4),
+                                         "roofline_mfma": {"bound": "mfma", "achieved": round(b["mlp_tflops"], 3),
+                                                           "peak": FP16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                                           "frac": round(b["mfma_frac"], 6),
+                                                           "executed_tflops": round(b["mfma_tflops_executed"], 3),
+                                                           "note": "algorithmic MLP FLOPs over the whole launch, "
+                                                                   "which the march bounds"}}
     if "adjoint_512" in extra:
         a = extra["adjoint_512"]
         legs_out["adjoint_512"] = {"bwd_mrays": round(a["bwd_mrays"], 3), "fwd_mrays": round(a["fwd_mrays"], 3),
                                    "ms_bwd": round(a["ms_bwd"], 4), "ms_fwd": round(a["ms_fwd"], 4),
-                                   "rays": a["rays"]}
+                                   "rays": a["rays"],
+                                   "roofline_hbm": {"fwd_gbs": round(a["fwd_alg_gbs"], 1),
+                                                    "bwd_gbs_lower_bound": round(a["bwd_alg_gbs"], 1),
+                                                    "peak": HBM_PEAK_GBS,
+                                                    "fwd_frac": round(a["fwd_alg_gbs"] / HBM_PEAK_GBS, 4),
+                                                    "bwd_frac_lower_bound": round(a["bwd_alg_gbs"] / HBM_PEAK_GBS, 4)}}
     if "large_1024" in extra:
         b = extra["large_1024"]
         legs_out["large_1024"] = {"mrays": round(b["mrays"], 3), "ms": round(b["ms"], 3),
