@@ -155,10 +155,14 @@ typedef struct {
 /* ---------------------------------------------------------------- handles */
 
 /* Creates a handle on the current HIP device.  It owns small device buffers
- * (camera table, tile counter, the backward pass's MLP partial sums and
- * per-ray dL/dC_d, dL/dV scratch, grown on demand), a cached HIP graph and
- * the tuning; nothing the caller passes in.  Calls on one handle should use
- * one stream (or the caller orders the streams). */
+ * (camera table, tile counter, the render's tile-order scratch, the backward
+ * pass's MLP partial sums and per-ray dL/dC_d, dL/dV scratch, the baking
+ * scratch), a cached HIP graph, timing events and the tuning; nothing the
+ * caller passes in.  The buffers are allocated on first use and grown when a
+ * call needs more (the growing call waits for the device first), so a call
+ * made inside a caller's stream capture must have been made once outside it
+ * with the same sizes.  Calls on one handle should use one stream (or the
+ * caller orders the streams). */
 int snerg_create(snerg_handle **out);
 int snerg_destroy(snerg_handle *h);
 
