@@ -11,7 +11,10 @@
  * then runs once per pixel on the composited colour, features and view
  * direction and its residual is added (Eq. 7, Section 4.2).  A backward
  * entry point gives gradients with respect to the MLP and a float copy of
- * the grid values, for fine-tuning by a pixel loss (Eq. 3, Section 5.5).
+ * the grid values, for fine-tuning by a pixel loss (Eq. 3, Section 5.5),
+ * with a squared-error loss and an Adam step beside it.  Two baking entry
+ * points turn a densely evaluated field into the grid: the empty-space and
+ * visibility culls of Section 5.3 and the 8-bit atlas of Section 5.4.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
