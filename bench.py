@@ -351,10 +351,11 @@ def leg_large(args, torch, S, W, O):
 
 
 def leg_nondeferred(args, torch, S, W, plain):
-    """The performance ablation of Section 6 on the plain 512^3 frame: the
-    view network on every composited sample rather than a single time per ray, in
-    FP32 and on FP16 MFMA tiles; the deferral speed-up against the deferred
-    FP32 frame and the per-sample network's FLOP rate."""
+    """The performance ablation of Section 6 on the plain 512^3 frame: no
+    view network at all, and the view network on every composited sample
+    rather than a single time per ray, in FP32 and on FP16 MFMA tiles; the
+    deferral speed-up against the deferred FP32 frame and the per-sample
+    network's FLOP rate."""
     cfg = W.config("plain512")
     g, cams, mlp = cfg["grid"], cfg["cams"], cfg["mlp"]
     h = S.Handle()
@@ -366,6 +367,13 @@ def leg_nondeferred(args, torch, S, W, plain):
     grid = dg.struct()
     active = plain["counters"]["active"]
     res = {}
+    # ablation row 1 of Section 6: no view-dependent network at all (diffuse colour only)
+    off = S.make_opts(mlp_on=False)
+    ms_off = time_launches(lambda: S.snerg_render(h, grid, m, carr, None, n, off, out), max(4, args.steps // 2), 2,
+                           torch)
+    res["mlp_off"] = dict(ms=ms_off, mrays=n / ms_off / 1e3, mlp_share_of_deferred_frame=1.0 - ms_off / plain["ms"])
+    log(f"no view network: {ms_off:.3f} ms/frame; the deferred network is {100 * (1 - ms_off / plain['ms']):.1f}% "
+        f"of the deferred frame")
     for name, fp16 in (("fp32", False), ("fp16_mfma", True)):
         opts = S.make_opts(fp16=fp16, per_sample_mlp=True)
         ms = time_launches(lambda: S.snerg_render(h, grid, m, carr, None, n, opts, out), max(4, args.steps // 2),
