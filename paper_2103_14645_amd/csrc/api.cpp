@@ -312,19 +312,12 @@ int render_impl(snerg_handle* h, const snerg_grid* grid, const float* mlp, const
         }
     }
     a.tile_order = order;
-    if (!(opts->flags & SNERG_FLAG_PERSISTENT)) {
-        a.mode = kModeTiles;
-        HIP_TRY(launch_tile_order(a, cls, counts, order, s));
-        HIP_TRY(timing_begin(h, s));
-        HIP_TRY(launch_render(a, vt, mlp_mode, wpg, 0, s));
-        HIP_TRY(timing_end(h, s));
-        return SNERG_OK;
-    }
-    a.mode = kModePersistent;
-    const int n_groups = h->n_cu * tu.groups_per_cu;
+    const bool persistent = (opts->flags & SNERG_FLAG_PERSISTENT) != 0;
+    a.mode = persistent ? kModePersistent : kModeTiles;
+    const int n_groups = persistent ? h->n_cu * tu.groups_per_cu : 0;
     if (!(opts->flags & SNERG_FLAG_GRAPH)) {
         HIP_TRY(launch_tile_order(a, cls, counts, order, s));
-        HIP_TRY(launch_fill_i32(h->d_counter, 1, 0, s));
+        if (persistent) HIP_TRY(launch_fill_i32(h->d_counter, 1, 0, s));
         HIP_TRY(timing_begin(h, s));
         HIP_TRY(launch_render(a, vt, mlp_mode, wpg, n_groups, s));
         HIP_TRY(timing_end(h, s));
@@ -345,7 +338,7 @@ int render_impl(snerg_handle* h, const snerg_grid* grid, const float* mlp, const
         hipGraph_t graph = nullptr;
         HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
         hipError_t e1 = launch_tile_order(a, cls, counts, order, h->cap_stream);
-        if (e1 == hipSuccess) e1 = launch_fill_i32(h->d_counter, 1, 0, h->cap_stream);
+        if (e1 == hipSuccess && persistent) e1 = launch_fill_i32(h->d_counter, 1, 0, h->cap_stream);
         hipError_t e2 = e1 == hipSuccess ? launch_render(a, vt, mlp_mode, wpg, n_groups, h->cap_stream) : e1;
         hipError_t e3 = hipStreamEndCapture(h->cap_stream, &graph);
         if (e2 != hipSuccess) {

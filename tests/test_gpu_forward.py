@@ -47,7 +47,7 @@ def test_tiny_launch_modes_agree_bitwise():
     dg = device_grid(g)
     base = gpu_render(dg, mlp, cams)
     n = base.shape[0]
-    for kw in (dict(persistent=True), dict(persistent=True, graph=True)):
+    for kw in (dict(persistent=True), dict(persistent=True, graph=True), dict(graph=True)):
         say(f"launch mode {kw}")
         assert np.array_equal(gpu_render(dg, mlp, cams, **kw), base)
     ids = np.random.default_rng(0).permutation(n)[: n // 3]
