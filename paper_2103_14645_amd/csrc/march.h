@@ -265,27 +265,33 @@ __host__ __device__ __forceinline__ int64_t march_ray(const GridArgs& g, const u
     return -1;
 }
 
-// Occupied macroblocks on the ray's lattice inside the grid, up to `cap`:
-// the macroblock walk of march_ray alone, without visiting samples and
-// without early stop (a cost estimate for scheduling, not part of any
-// result).
-__device__ __forceinline__ int32_t occupied_blocks_on_ray(const GridArgs& g, const uint2* occ, const int64_t o[3],
-                                                          const int32_t s[3], int32_t cap) {
+// Occupied macroblocks whose first sample on the ray's lattice lies in the
+// part [k0, k1] of the lattice indices inside the grid: the macroblock walk
+// of march_ray alone, without visiting samples and without early stop (a cost
+// estimate for scheduling, not part of any result).  Splitting [klo, khi]
+// into parts and adding their counts gives the ray's count exactly: a block
+// that a part starts in the middle of belongs to the part before.
+__host__ __device__ __forceinline__ int32_t occupied_blocks_on_ray(const GridArgs& g, const uint2* occ, const int64_t o[3],
+                                                          const int32_t s[3], int part, int n_parts) {
     const int bs = 16 + g.logB;
     const int64_t L = int64_t(g.N) << 16;
     int64_t klo, khi;
     if (!entry_range(o, s, L, klo, khi)) return 0;
+    const int64_t len = khi - klo + 1;
+    const int64_t k0 = klo + len * part / n_parts, k1 = klo + len * (part + 1) / n_parts - 1;
+    if (k0 > k1) return 0;
     float inv[3];
     int32_t P[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int32_t sa = s[a] < 0 ? -s[a] : s[a];
         inv[a] = sa != 0 ? 1.0f / float(sa) : 0.0f;
-        P[a] = int32_t(o[a] + klo * int64_t(s[a]));
+        P[a] = int32_t(o[a] + k0 * int64_t(s[a]));
     }
-    const int32_t kend = int32_t(khi - klo);
+    const int32_t kend = int32_t(k1 - k0);
     int32_t k = 0, count = 0;
-    while (k <= kend && count < cap) {
+    bool first = k0 > klo;
+    while (k <= kend) {
         int32_t b[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) b[a] = P[a] >> bs;
@@ -293,7 +299,13 @@ __device__ __forceinline__ int32_t occupied_blocks_on_ray(const GridArgs& g, con
             break;
         const int32_t nstep = block_steps(P, s, inv, b, bs);
         const int32_t lin = (b[2] * g.G + b[1]) * g.G + b[0];
-        count += int32_t((occ[lin >> 5].x >> (lin & 31)) & 1u);
+        bool counted = ((occ[lin >> 5].x >> (lin & 31)) & 1u) != 0;
+        if (first) {  // entered in an earlier part?
+            counted = counted && (((P[0] - s[0]) >> bs) != b[0] || ((P[1] - s[1]) >> bs) != b[1] ||
+                                  ((P[2] - s[2]) >> bs) != b[2]);
+            first = false;
+        }
+        count += int32_t(counted);
 #pragma unroll
         for (int a = 0; a < 3; ++a) P[a] += nstep * s[a];
         k += nstep;

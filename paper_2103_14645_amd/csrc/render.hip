@@ -247,15 +247,20 @@ __global__ __launch_bounds__(256) void k_trace(RenderArgs a) {
 // issued late, they run on an emptying machine and set the frame time.
 // Tiles are therefore sorted by a cost class, the number of occupied
 // macroblocks on the tile's centre ray (capped at 15), and the render takes
-// them in decreasing class.  Pass 1: one lane per tile computes its class
-// and the class histogram.  Pass 2: each workgroup reserves, per class, a
+// them in decreasing class.  Pass 1: eight lanes per tile walk eighths of
+// its centre ray and add their counts into its class; the class histogram.  Pass 2: each workgroup reserves, per class, a
 // range after all tiles of higher classes and writes its tiles there.
-__global__ __launch_bounds__(64) void k_tile_cost(RenderArgs a, uint8_t* __restrict__ cls,
+constexpr int kCostParts = 8;  // lanes per tile, each walking a part of the centre ray
+
+__global__ __launch_bounds__(256) void k_tile_cost(RenderArgs a, uint8_t* __restrict__ cls,
                                                    int32_t* __restrict__ counts) {
     __shared__ int32_t hist[kCostClasses];
     if (threadIdx.x < kCostClasses) hist[threadIdx.x] = 0;
     const uint2* occ = stage_occupancy(a.grid);  // synchronises
-    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t t = gid / kCostParts;
+    const int part = int(gid % kCostParts);
+    int32_t k = 0;
     if (t < a.total_tiles) {
         const int ci = find_camera_by_tile(a.cams, a.n_cams, t);
         const DevCamera& c = a.cams[ci];
@@ -267,7 +272,13 @@ __global__ __launch_bounds__(64) void k_tile_cost(RenderArgs a, uint8_t* __restr
         int32_t sd[3];
         float d[3];
         ray_setup(c, a.grid.N, px, py, o, sd, d);
-        const int32_t k = occupied_blocks_on_ray(a.grid, occ, o, sd, kCostClasses - 1);
+        k = occupied_blocks_on_ray(a.grid, occ, o, sd, part, kCostParts);
+    }
+    // the parts of one tile are adjacent lanes of one wavefront
+#pragma unroll
+    for (int m = 1; m < kCostParts; m <<= 1) k += __shfl_xor(k, m);
+    if (t < a.total_tiles && part == 0) {
+        k = min(k, kCostClasses - 1);
         cls[t] = uint8_t(k);
         atomicAdd(&hist[k], 1);
     }
@@ -310,10 +321,10 @@ __global__ __launch_bounds__(256) void k_tile_sort(const uint8_t* __restrict__ c
 
 hipError_t launch_tile_order(const RenderArgs& a, uint8_t* cls, int32_t* counts, int32_t* order, hipStream_t s) {
     if (a.total_tiles <= 0 || !order) return hipSuccess;
-    // one wavefront per workgroup: the walk is a latency chain, so spread it over many CUs
-    const unsigned cblocks = unsigned((a.total_tiles + 63) / 64);
+    // kCostParts lanes per tile: the walk is a latency chain, so spread it over many lanes
+    const unsigned cblocks = unsigned((a.total_tiles * kCostParts + 255) / 256);
     const size_t lds = size_t(a.grid.n_words) * sizeof(uint2);
-    hipLaunchKernelGGL(k_tile_cost, dim3(cblocks), dim3(64), lds, s, a, cls, counts);
+    hipLaunchKernelGGL(k_tile_cost, dim3(cblocks), dim3(256), lds, s, a, cls, counts);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const unsigned blocks = unsigned((a.total_tiles + 255) / 256);
