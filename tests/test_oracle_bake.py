@@ -39,6 +39,20 @@ def test_axis_ray_transmittance_closed_form():
     assert np.all(vis[mask] == 0.0) and np.all(np.isinf(depth[mask]))
 
 
+def test_camera_inside_the_grid_sees_from_its_own_voxel():
+    # eye on the face between voxels 2 and 3 along x, looking +x: sample k sits
+    # at x = 3 + k/2 voxels (k = 0 included), so voxel x >= 3 is entered after
+    # 2 (x - 3) samples and the voxels behind the eye see nothing
+    N, s0, yv, zv = 16, 0.25, 7, 4
+    sigma = np.full((N, N, N), s0)
+    cam = axis_camera(N, +1, yv, zv)
+    cam.eye = np.array([3.0 * 2.0 / N - 1.0, cam.eye[1], cam.eye[2]])
+    vis, depth = K.voxel_visibility(sigma, [cam])
+    x = np.arange(3, N)
+    np.testing.assert_array_equal(depth[zv, yv, 3:], 2 * (x - 3) * s0)
+    assert np.all(vis[zv, yv, :3] == 0.0) and vis[zv, yv, 3] == 1.0
+
+
 def test_visibility_is_the_maximum_over_cameras():
     # From the -x side voxel x is entered after 30 - 2x samples (the ray's
     # first sample sits in the upper half of voxel N - 1).
