@@ -265,6 +265,95 @@ __host__ __device__ __forceinline__ int64_t march_ray(const GridArgs& g, const u
     return -1;
 }
 
+// The samples march_ray visits, in the same order, from one flat loop: on
+// each trip a lane either enters its next macroblock (and, when that one is
+// occupied, goes on to read the distance byte of its first cell) or reads
+// the distance byte of its next cell; a zero byte is an active cell and the
+// lane takes the sample on the same trip.  With the macroblock walk and the
+// in-block steps in one loop the lanes of a wavefront no longer wait for
+// each other at every macroblock face, so the sample code runs with more
+// lanes at once.  on_sample as for march_ray.
+template <typename OnSample>
+__device__ __forceinline__ void march_ray_flat(const GridArgs& g, const uint2* occ, const int64_t o[3],
+                                               const int32_t s[3], OnSample&& on_sample) {
+    const int bs = 16 + g.logB;
+    const int64_t L = int64_t(g.N) << 16;
+    const uint32_t nc = uint32_t(g.Bc), ncc = nc * nc;
+    int64_t klo, khi;
+    if (!entry_range(o, s, L, klo, khi)) return;
+    float inv[3];
+    int32_t P[3];
+    int32_t smax = 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int32_t sa = s[a] < 0 ? -s[a] : s[a];
+        smax = sa > smax ? sa : smax;
+        inv[a] = sa != 0 ? 1.0f / float(sa) : 0.0f;
+        P[a] = int32_t(o[a] + klo * int64_t(s[a]));  // inside [0, N 2^16)
+    }
+    const float inv_smax = 1.0f / float(smax);
+    const int32_t kend = int32_t(khi - klo);  // relative, inclusive
+    int32_t k = 0;     // first relative sample of the next macroblock
+    int32_t kk = 0;    // relative sample at q
+    int32_t left = 0;  // samples of the current occupied macroblock from q on
+    int32_t r = -1;
+    int32_t q[3] = {0, 0, 0};
+    const uint8_t* __restrict__ dist = g.rec;
+    // One if-region per kind of work and a single loop flag (no early exit
+    // from the loop body) keep the loop flat in the generated code.
+    bool live = true;
+    while (live) {
+        bool inside = left > 0;
+        if (!inside) {
+            int32_t b[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) b[a] = P[a] >> bs;
+            // the end of the ray, and the same guards as march_ray
+            if (k > kend || (unsigned)b[0] >= (unsigned)g.G || (unsigned)b[1] >= (unsigned)g.G ||
+                (unsigned)b[2] >= (unsigned)g.G) {
+                live = false;
+            } else {
+                int32_t nstep = block_steps(P, s, inv, b, bs);
+                while (nstep > 1 && (((P[0] + (nstep - 1) * s[0]) >> bs) != b[0] ||
+                                     ((P[1] + (nstep - 1) * s[1]) >> bs) != b[1] ||
+                                     ((P[2] + (nstep - 1) * s[2]) >> bs) != b[2]))
+                    --nstep;
+                const int32_t kn = (k + nstep) < (kend + 1) ? (k + nstep) : (kend + 1);
+                const int32_t lin = (b[2] * g.G + b[1]) * g.G + b[0];
+                r = block_rank(occ, lin, g.n_blocks);
+                if (r >= 0) {
+                    dist = g.rec + int64_t(r) * g.rec_stride;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) q[a] = P[a] - (b[a] << bs) + 32768;  // padded Q16 coordinate
+                    left = kn - k;
+                    kk = k;
+                    inside = true;
+                }
+                const int32_t adv = kn - k;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) P[a] += adv * s[a];  // |adv s| <= B 2^16 + |s|
+                k = kn;
+            }
+        }
+        if (inside) {
+            const int32_t p[3] = {q[0] >> 16, q[1] >> 16, q[2] >> 16};
+            const int32_t d = dist[cell_index(p, nc, ncc)];
+            int32_t adv = 1;
+            if (d == 0) {
+                const int32_t fr[3] = {q[0] & 0xFFFF, q[1] & 0xFFFF, q[2] & 0xFFFF};
+                if (on_sample(klo + kk, r, dist + g.dist_bytes, p, fr)) live = false;
+            } else {
+                adv = skip_steps(d, smax, inv_smax);
+                adv = adv < left ? adv : left;
+            }
+            kk += adv;
+            left -= adv;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) q[a] += adv * s[a];
+        }
+    }
+}
+
 // Occupied macroblocks whose first sample on the ray's lattice lies in the
 // part [k0, k1] of the lattice indices inside the grid: the macroblock walk
 // of march_ray alone, without visiting samples and without early stop (a cost

@@ -43,8 +43,8 @@ __device__ __forceinline__ void march_composite(const RenderArgs& a, const uint2
     const uint8_t* cached = nullptr;
     Corners8 cn;
     const uint32_t nb = uint32_t(g.Bp), nbb = nb * nb;
-    march_ray(
-        g, occ, o, s, [](int32_t, bool) {}, [](int32_t) {},
+    march_ray_flat(
+        g, occ, o, s,
         [&](int64_t, int32_t, const uint8_t* vox, const int32_t p[3], const int32_t fr[3]) {
             Sample smp;
             if (VT == 0) {
