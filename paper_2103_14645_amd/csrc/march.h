@@ -265,6 +265,13 @@ __host__ __device__ __forceinline__ int64_t march_ray(const GridArgs& g, const u
     return -1;
 }
 
+// a * b for operands that fit 24-bit signed integers (|a|, |b| < 2^23) with
+// a product inside int32: the sign-extension from bit 23 is an identity on
+// such values and lets the compiler use the 24-bit multiplier.
+__host__ __device__ __forceinline__ int32_t mul_s24(int32_t a, int32_t b) {
+    return (int32_t(uint32_t(a) << 8) >> 8) * (int32_t(uint32_t(b) << 8) >> 8);
+}
+
 // The samples march_ray visits, in the same order, from one flat loop: on
 // each trip a lane either enters its next macroblock (and, when that one is
 // occupied, goes on to read the distance byte of its first cell) or reads
@@ -273,27 +280,59 @@ __host__ __device__ __forceinline__ int64_t march_ray(const GridArgs& g, const u
 // in-block steps in one loop the lanes of a wavefront no longer wait for
 // each other at every macroblock face, so the sample code runs with more
 // lanes at once.  on_sample as for march_ray.
+//
+// The macroblock walk is incremental.  With X_a(k) = P_a + k s_a the Q16
+// position of relative sample k and W = B 2^16 the macroblock edge, the ray
+// leaves its macroblock along axis a at kc_a, the smallest k with
+// k |s_a| >= F_a, where F_a = (b_a + 1) W - P_a for s_a > 0 and
+// F_a = P_a - b_a W + 1 for s_a < 0.  Crossing that face adds W to F_a, and
+// with Q_a = floor(W / |s_a|) the next crossing is kc_a + Q_a or
+// kc_a + Q_a + 1, whichever is the first to satisfy the inequality.  The
+// next macroblock starts at min_a kc_a, as in march_ray, and every axis
+// whose kc_a equals it changes macroblock there.
 template <typename OnSample>
-__device__ __forceinline__ void march_ray_flat(const GridArgs& g, const uint2* occ, const int64_t o[3],
-                                               const int32_t s[3], OnSample&& on_sample) {
+__host__ __device__ __forceinline__ void march_ray_flat(const GridArgs& g, const uint2* occ, const int64_t o[3],
+                                                        const int32_t s[3], OnSample&& on_sample) {
     const int bs = 16 + g.logB;
     const int64_t L = int64_t(g.N) << 16;
     const uint32_t nc = uint32_t(g.Bc), ncc = nc * nc;
+    const int32_t W = int32_t(1) << bs;
     int64_t klo, khi;
     if (!entry_range(o, s, L, klo, khi)) return;
-    float inv[3];
-    int32_t P[3];
+    int32_t P[3], b[3], kc[3], F[3], Q[3], as[3], dlin[3];
     int32_t smax = 1;
+    const int32_t gstride[3] = {1, g.G, g.G * g.G};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int32_t sa = s[a] < 0 ? -s[a] : s[a];
+        as[a] = sa;
         smax = sa > smax ? sa : smax;
-        inv[a] = sa != 0 ? 1.0f / float(sa) : 0.0f;
         P[a] = int32_t(o[a] + klo * int64_t(s[a]));  // inside [0, N 2^16)
+        b[a] = P[a] >> bs;
+        const float inv = sa != 0 ? 1.0f / float(sa) : 0.0f;
+        if (s[a] > 0) {
+            F[a] = ((b[a] + 1) << bs) - P[a];  // in (0, W]
+            kc[a] = steps_to_reach(F[a], sa, inv);
+            dlin[a] = gstride[a];
+        } else if (s[a] < 0) {
+            F[a] = P[a] - (b[a] << bs) + 1;  // in [1, W]
+            kc[a] = steps_to_reach(F[a], sa, inv);
+            dlin[a] = -gstride[a];
+        } else {
+            F[a] = 0;
+            kc[a] = 0x7fffffff;
+            dlin[a] = 0;
+        }
+        // Q = floor(W / |s|)
+        int32_t q = sa != 0 ? int32_t(__builtin_floorf(float(W) * inv)) : 0;
+        if (sa != 0 && (q + 1) * sa <= W) ++q;
+        if (sa != 0 && q * sa > W) --q;
+        Q[a] = q;
     }
     const float inv_smax = 1.0f / float(smax);
     const int32_t kend = int32_t(khi - klo);  // relative, inclusive
-    int32_t k = 0;     // first relative sample of the next macroblock
+    int32_t lin = (b[2] * g.G + b[1]) * g.G + b[0];
+    int32_t k = 0;     // first relative sample of the macroblock b
     int32_t kk = 0;    // relative sample at q
     int32_t left = 0;  // samples of the current occupied macroblock from q on
     int32_t r = -1;
@@ -305,33 +344,33 @@ __device__ __forceinline__ void march_ray_flat(const GridArgs& g, const uint2* o
     while (live) {
         bool inside = left > 0;
         if (!inside) {
-            int32_t b[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) b[a] = P[a] >> bs;
-            // the end of the ray, and the same guards as march_ray
+            // the end of the ray, and the same guard as march_ray
             if (k > kend || (unsigned)b[0] >= (unsigned)g.G || (unsigned)b[1] >= (unsigned)g.G ||
                 (unsigned)b[2] >= (unsigned)g.G) {
                 live = false;
             } else {
-                int32_t nstep = block_steps(P, s, inv, b, bs);
-                while (nstep > 1 && (((P[0] + (nstep - 1) * s[0]) >> bs) != b[0] ||
-                                     ((P[1] + (nstep - 1) * s[1]) >> bs) != b[1] ||
-                                     ((P[2] + (nstep - 1) * s[2]) >> bs) != b[2]))
-                    --nstep;
-                const int32_t kn = (k + nstep) < (kend + 1) ? (k + nstep) : (kend + 1);
-                const int32_t lin = (b[2] * g.G + b[1]) * g.G + b[0];
+                int32_t kn = kc[0] < kc[1] ? kc[0] : kc[1];
+                kn = kn < kc[2] ? kn : kc[2];
+                kn = kn < kend + 1 ? kn : kend + 1;
                 r = block_rank(occ, lin, g.n_blocks);
                 if (r >= 0) {
                     dist = g.rec + int64_t(r) * g.rec_stride;
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) q[a] = P[a] - (b[a] << bs) + 32768;  // padded Q16 coordinate
+                    for (int a = 0; a < 3; ++a) q[a] = P[a] + mul_s24(k, s[a]) - (b[a] << bs) + 32768;  // padded Q16
                     left = kn - k;
                     kk = k;
                     inside = true;
                 }
-                const int32_t adv = kn - k;
 #pragma unroll
-                for (int a = 0; a < 3; ++a) P[a] += adv * s[a];  // |adv s| <= B 2^16 + |s|
+                for (int a = 0; a < 3; ++a) {
+                    if (kc[a] == kn) {
+                        b[a] += s[a] > 0 ? 1 : -1;
+                        lin += dlin[a];
+                        F[a] += W;
+                        const int32_t c = kc[a] + Q[a];
+                        kc[a] = mul_s24(c, as[a]) >= F[a] ? c : c + 1;
+                    }
+                }
                 k = kn;
             }
         }
@@ -349,7 +388,7 @@ __device__ __forceinline__ void march_ray_flat(const GridArgs& g, const uint2* o
             kk += adv;
             left -= adv;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) q[a] += adv * s[a];
+            for (int a = 0; a < 3; ++a) q[a] += mul_s24(adv, s[a]);
         }
     }
 }
