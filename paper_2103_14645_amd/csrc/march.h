@@ -297,32 +297,24 @@ __host__ __device__ __forceinline__ void march_ray_flat(const GridArgs& g, const
     const int64_t L = int64_t(g.N) << 16;
     const uint32_t nc = uint32_t(g.Bc), ncc = nc * nc;
     const int32_t W = int32_t(1) << bs;
+    const uint32_t G3 = uint32_t(g.G) * uint32_t(g.G) * uint32_t(g.G);
     int64_t klo, khi;
     if (!entry_range(o, s, L, klo, khi)) return;
-    int32_t P[3], b[3], kc[3], F[3], Q[3], as[3], dlin[3];
-    int32_t smax = 1;
+    int32_t kc[3], F[3], Q[3];
+    int32_t smax = 1, lin = 0;
     const int32_t gstride[3] = {1, g.G, g.G * g.G};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int32_t sa = s[a] < 0 ? -s[a] : s[a];
-        as[a] = sa;
         smax = sa > smax ? sa : smax;
-        P[a] = int32_t(o[a] + klo * int64_t(s[a]));  // inside [0, N 2^16)
-        b[a] = P[a] >> bs;
+        const int32_t P = int32_t(o[a] + klo * int64_t(s[a]));  // inside [0, N 2^16)
+        const int32_t b = P >> bs;
+        lin += b * gstride[a];
         const float inv = sa != 0 ? 1.0f / float(sa) : 0.0f;
-        if (s[a] > 0) {
-            F[a] = ((b[a] + 1) << bs) - P[a];  // in (0, W]
-            kc[a] = steps_to_reach(F[a], sa, inv);
-            dlin[a] = gstride[a];
-        } else if (s[a] < 0) {
-            F[a] = P[a] - (b[a] << bs) + 1;  // in [1, W]
-            kc[a] = steps_to_reach(F[a], sa, inv);
-            dlin[a] = -gstride[a];
-        } else {
-            F[a] = 0;
-            kc[a] = 0x7fffffff;
-            dlin[a] = 0;
-        }
+        // F as defined above; for s = 0 the s < 0 form, which then only
+        // serves to place the sample inside its macroblock
+        F[a] = s[a] > 0 ? ((b + 1) << bs) - P : P - (b << bs) + 1;  // in [1, W]
+        kc[a] = sa != 0 ? steps_to_reach(F[a], sa, inv) : 0x7fffffff;
         // Q = floor(W / |s|)
         int32_t q = sa != 0 ? int32_t(__builtin_floorf(float(W) * inv)) : 0;
         if (sa != 0 && (q + 1) * sa <= W) ++q;
@@ -331,8 +323,7 @@ __host__ __device__ __forceinline__ void march_ray_flat(const GridArgs& g, const
     }
     const float inv_smax = 1.0f / float(smax);
     const int32_t kend = int32_t(khi - klo);  // relative, inclusive
-    int32_t lin = (b[2] * g.G + b[1]) * g.G + b[0];
-    int32_t k = 0;     // first relative sample of the macroblock b
+    int32_t k = 0;     // first relative sample of the current macroblock
     int32_t kk = 0;    // relative sample at q
     int32_t left = 0;  // samples of the current occupied macroblock from q on
     int32_t r = -1;
@@ -344,9 +335,9 @@ __host__ __device__ __forceinline__ void march_ray_flat(const GridArgs& g, const
     while (live) {
         bool inside = left > 0;
         if (!inside) {
-            // the end of the ray, and the same guard as march_ray
-            if (k > kend || (unsigned)b[0] >= (unsigned)g.G || (unsigned)b[1] >= (unsigned)g.G ||
-                (unsigned)b[2] >= (unsigned)g.G) {
+            // the end of the ray; the index guard keeps the table reads in
+            // bounds should the exact walk ever leave the grid
+            if (k > kend || uint32_t(lin) >= G3) {
                 live = false;
             } else {
                 int32_t kn = kc[0] < kc[1] ? kc[0] : kc[1];
@@ -355,8 +346,10 @@ __host__ __device__ __forceinline__ void march_ray_flat(const GridArgs& g, const
                 r = block_rank(occ, lin, g.n_blocks);
                 if (r >= 0) {
                     dist = g.rec + int64_t(r) * g.rec_stride;
+                    // Q16 position of sample k inside the macroblock, + 2^15 for the padding
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) q[a] = P[a] + mul_s24(k, s[a]) - (b[a] << bs) + 32768;  // padded Q16
+                    for (int a = 0; a < 3; ++a)
+                        q[a] = (s[a] > 0 ? W - F[a] : F[a] - 1) + mul_s24(k, s[a]) + 32768;
                     left = kn - k;
                     kk = k;
                     inside = true;
@@ -364,11 +357,11 @@ __host__ __device__ __forceinline__ void march_ray_flat(const GridArgs& g, const
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     if (kc[a] == kn) {
-                        b[a] += s[a] > 0 ? 1 : -1;
-                        lin += dlin[a];
+                        lin += s[a] > 0 ? gstride[a] : -gstride[a];
                         F[a] += W;
                         const int32_t c = kc[a] + Q[a];
-                        kc[a] = mul_s24(c, as[a]) >= F[a] ? c : c + 1;
+                        const int32_t cs = mul_s24(c, s[a]);  // c |s| = sign(s) c s
+                        kc[a] = (s[a] > 0 ? cs : -cs) >= F[a] ? c : c + 1;
                     }
                 }
                 k = kn;
