@@ -554,7 +554,7 @@ __global__ __launch_bounds__(64 * kAggWaves) void k_march_backward(BackwardArgs 
     const float t_stop = a.opts.t_stop;
     const bool early = a.opts.early_stop != 0;
     const bool nn_gate = a.opts.nn_gate != 0;
-    march_ray_sync(
+    march_ray_flat_sync(
         g, s_occ, live, o, s,
         [&](int64_t, int32_t rk, const uint8_t* vox, const int32_t p[3], const int32_t fr[3]) {
             Sample smp;

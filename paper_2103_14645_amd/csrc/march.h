@@ -290,49 +290,70 @@ __host__ __device__ __forceinline__ int32_t mul_s24(int32_t a, int32_t b) {
 // kc_a + Q_a + 1, whichever is the first to satisfy the inequality.  The
 // next macroblock starts at min_a kc_a, as in march_ray, and every axis
 // whose kc_a equals it changes macroblock there.
-template <typename OnSample>
-__host__ __device__ __forceinline__ void march_ray_flat(const GridArgs& g, const uint2* occ, const int64_t o[3],
-                                                        const int32_t s[3], OnSample&& on_sample) {
-    const int bs = 16 + g.logB;
-    const int64_t L = int64_t(g.N) << 16;
-    const uint32_t nc = uint32_t(g.Bc), ncc = nc * nc;
-    const int32_t W = int32_t(1) << bs;
-    const uint32_t G3 = uint32_t(g.G) * uint32_t(g.G) * uint32_t(g.G);
-    int64_t klo, khi;
-    if (!entry_range(o, s, L, klo, khi)) return;
+struct FlatWalk {
     int32_t kc[3], F[3], Q[3];
-    int32_t smax = 1, lin = 0;
-    const int32_t gstride[3] = {1, g.G, g.G * g.G};
+    int32_t smax, lin, kend;
+    int32_t k;     // first relative sample of the current macroblock
+    int32_t kk;    // relative sample at q
+    int32_t left;  // samples of the current occupied macroblock from q on
+    int32_t r;
+    int32_t q[3];
+    int64_t klo;
+    float inv_smax;
+    const uint8_t* __restrict__ dist;
+
+    // Sets up the walk of a ray; false when it misses the grid.
+    __host__ __device__ __forceinline__ bool init(const GridArgs& g, const int64_t o[3], const int32_t s[3]) {
+        const int bs = 16 + g.logB;
+        const int32_t W = int32_t(1) << bs;
+        int64_t khi;
+        if (!entry_range(o, s, int64_t(g.N) << 16, klo, khi)) return false;
+        const int32_t gstride[3] = {1, g.G, g.G * g.G};
+        smax = 1;
+        lin = 0;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const int32_t sa = s[a] < 0 ? -s[a] : s[a];
-        smax = sa > smax ? sa : smax;
-        const int32_t P = int32_t(o[a] + klo * int64_t(s[a]));  // inside [0, N 2^16)
-        const int32_t b = P >> bs;
-        lin += b * gstride[a];
-        const float inv = sa != 0 ? 1.0f / float(sa) : 0.0f;
-        // F as defined above; for s = 0 the s < 0 form, which then only
-        // serves to place the sample inside its macroblock
-        F[a] = s[a] > 0 ? ((b + 1) << bs) - P : P - (b << bs) + 1;  // in [1, W]
-        kc[a] = sa != 0 ? steps_to_reach(F[a], sa, inv) : 0x7fffffff;
-        // Q = floor(W / |s|)
-        int32_t q = sa != 0 ? int32_t(__builtin_floorf(float(W) * inv)) : 0;
-        if (sa != 0 && (q + 1) * sa <= W) ++q;
-        if (sa != 0 && q * sa > W) --q;
-        Q[a] = q;
+        for (int a = 0; a < 3; ++a) {
+            const int32_t sa = s[a] < 0 ? -s[a] : s[a];
+            smax = sa > smax ? sa : smax;
+            const int32_t P = int32_t(o[a] + klo * int64_t(s[a]));  // inside [0, N 2^16)
+            const int32_t b = P >> bs;
+            lin += b * gstride[a];
+            const float inv = sa != 0 ? 1.0f / float(sa) : 0.0f;
+            // F as defined above; for s = 0 the s < 0 form, which then only
+            // serves to place the sample inside its macroblock
+            F[a] = s[a] > 0 ? ((b + 1) << bs) - P : P - (b << bs) + 1;  // in [1, W]
+            kc[a] = sa != 0 ? steps_to_reach(F[a], sa, inv) : 0x7fffffff;
+            // Q = floor(W / |s|)
+            int32_t qa = sa != 0 ? int32_t(__builtin_floorf(float(W) * inv)) : 0;
+            if (sa != 0 && (qa + 1) * sa <= W) ++qa;
+            if (sa != 0 && qa * sa > W) --qa;
+            Q[a] = qa;
+        }
+        inv_smax = 1.0f / float(smax);
+        kend = int32_t(khi - klo);  // relative, inclusive
+        k = 0;
+        kk = 0;
+        left = 0;
+        r = -1;
+        q[0] = q[1] = q[2] = 0;
+        dist = g.rec;
+        return true;
     }
-    const float inv_smax = 1.0f / float(smax);
-    const int32_t kend = int32_t(khi - klo);  // relative, inclusive
-    int32_t k = 0;     // first relative sample of the current macroblock
-    int32_t kk = 0;    // relative sample at q
-    int32_t left = 0;  // samples of the current occupied macroblock from q on
-    int32_t r = -1;
-    int32_t q[3] = {0, 0, 0};
-    const uint8_t* __restrict__ dist = g.rec;
-    // One if-region per kind of work and a single loop flag (no early exit
-    // from the loop body) keep the loop flat in the generated code.
-    bool live = true;
-    while (live) {
+
+    // One trip: enter the next macroblock (going on to its first cell when
+    // it is occupied) or step to the next cell; on an active cell hand the
+    // sample to on_sample.  One if-region per kind of work and no early
+    // exit keep the caller's loop flat in the generated code.  Returns false
+    // once the ray has ended or on_sample asked to stop.
+    template <typename OnSample>
+    __host__ __device__ __forceinline__ bool trip(const GridArgs& g, const uint2* occ, const int32_t s[3],
+                                                  OnSample&& on_sample) {
+        const int bs = 16 + g.logB;
+        const int32_t W = int32_t(1) << bs;
+        const uint32_t nc = uint32_t(g.Bc), ncc = nc * nc;
+        const uint32_t G3 = uint32_t(g.G) * uint32_t(g.G) * uint32_t(g.G);
+        const int32_t gstride[3] = {1, g.G, g.G * g.G};
+        bool live = true;
         bool inside = left > 0;
         if (!inside) {
             // the end of the ray; the index guard keeps the table reads in
@@ -383,6 +404,33 @@ __host__ __device__ __forceinline__ void march_ray_flat(const GridArgs& g, const
 #pragma unroll
             for (int a = 0; a < 3; ++a) q[a] += mul_s24(adv, s[a]);
         }
+        return live;
+    }
+};
+
+template <typename OnSample>
+__host__ __device__ __forceinline__ void march_ray_flat(const GridArgs& g, const uint2* occ, const int64_t o[3],
+                                                        const int32_t s[3], OnSample&& on_sample) {
+    FlatWalk w;
+    bool live = w.init(g, o, s);
+    while (live) live = w.trip(g, occ, s, on_sample);
+}
+
+// march_ray_flat made convergent across the wavefront: every live lane
+// makes one trip per iteration, then all 64 lanes call on_sync() together,
+// which may therefore use wavefront-wide operations.  `live` false marks a
+// lane without a ray.  on_sample as for march_ray; returning true ends the
+// lane's march, and so does on_sync() returning true (after the samples
+// handed over so far).
+template <typename OnSample, typename OnSync>
+__device__ __forceinline__ void march_ray_flat_sync(const GridArgs& g, const uint2* occ, bool live,
+                                                    const int64_t o[3], const int32_t s[3], OnSample&& on_sample,
+                                                    OnSync&& on_sync) {
+    FlatWalk w;
+    if (live) live = w.init(g, o, s);
+    while (__any(live)) {
+        if (live) live = w.trip(g, occ, s, on_sample);
+        if (on_sync()) live = false;
     }
 }
 

@@ -108,7 +108,7 @@ __global__ __launch_bounds__(256) void k_render_ps(RenderArgs a) {
         PsAccum st = {{0.f, 0.f, 0.f}, 1.0f, false};
         bool pending = false;
         float pc[3] = {0.f, 0.f, 0.f}, pv[4] = {0.f, 0.f, 0.f, 0.f}, psig = 0.f;
-        march_ray_sync(
+        march_ray_flat_sync(
             g, s_occ, valid, o, s,
             [&](int64_t, int32_t, const uint8_t* vox, const int32_t p[3], const int32_t fr[3]) {
                 Sample smp;
