@@ -1,7 +1,9 @@
 // The per-ray march shared by the forward, trace and backward kernels:
-// integer lattice traversal with macroblock skipping, the cell-mask
-// pre-test, the 8-corner gather from the padded block, the exact
-// active-sample predicate and trilinear weights.
+// integer lattice traversal with macroblock skipping and distance-field
+// skipping inside macroblocks (march_ray, and the single-loop walk
+// FlatWalk that the render and adjoint kernels run), the 8-corner gather
+// from the padded block, the exact active-sample predicate and trilinear
+// weights.
 #pragma once
 
 #include "snerg_dev.h"
@@ -480,99 +482,6 @@ __host__ __device__ __forceinline__ int32_t occupied_blocks_on_ray(const GridArg
         k += nstep;
     }
     return count;
-}
-
-// The same visit sequence as march_ray, with both loops made convergent
-// across the wavefront: every lane runs one macroblock step per outer trip
-// and one in-block step per inner trip (lanes with nothing to do idle), and
-// after each inner trip all 64 lanes call on_sync() together, which may
-// therefore use wavefront-wide operations.  `live` false marks a lane
-// without a ray.  on_sample as for march_ray; returning true ends the
-// lane's march, and so does on_sync() returning true (after the samples
-// handed over so far).
-template <typename OnSample, typename OnSync>
-__device__ __forceinline__ void march_ray_sync(const GridArgs& g, const uint2* occ, bool live, const int64_t o[3],
-                                               const int32_t s[3], OnSample&& on_sample, OnSync&& on_sync) {
-    const int bs = 16 + g.logB;
-    const int64_t L = int64_t(g.N) << 16;
-    const uint32_t nc = uint32_t(g.Bc), ncc = nc * nc;
-    int64_t klo = 0, khi = -1;
-    if (live) live = entry_range(o, s, L, klo, khi);
-    float inv[3];
-    int32_t P[3];
-    int32_t smax = 1;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const int32_t sa = s[a] < 0 ? -s[a] : s[a];
-        smax = sa > smax ? sa : smax;
-        inv[a] = sa != 0 ? 1.0f / float(sa) : 0.0f;
-        P[a] = live ? int32_t(o[a] + klo * int64_t(s[a])) : 0;
-    }
-    const float inv_smax = 1.0f / float(smax);
-    const int32_t kend = live ? int32_t(khi - klo) : -1;
-    int32_t k = 0;
-    for (;;) {
-        live = live && k <= kend;
-        if (!__any(live)) break;
-        int32_t kn = k, kk = k;
-        int32_t left = 0, r = -1;
-        int32_t q[3] = {0, 0, 0};
-        const uint8_t* __restrict__ dist = g.rec;
-        if (live) {
-            int32_t b[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) b[a] = P[a] >> bs;
-            if ((unsigned)b[0] >= (unsigned)g.G || (unsigned)b[1] >= (unsigned)g.G || (unsigned)b[2] >= (unsigned)g.G) {
-                live = false;
-            } else {
-                int32_t nstep = block_steps(P, s, inv, b, bs);
-                while (nstep > 1 && (((P[0] + (nstep - 1) * s[0]) >> bs) != b[0] ||
-                                     ((P[1] + (nstep - 1) * s[1]) >> bs) != b[1] ||
-                                     ((P[2] + (nstep - 1) * s[2]) >> bs) != b[2]))
-                    --nstep;
-                kn = (k + nstep) < (kend + 1) ? (k + nstep) : (kend + 1);
-                const int32_t lin = (b[2] * g.G + b[1]) * g.G + b[0];
-                r = block_rank(occ, lin, g.n_blocks);
-                if (r >= 0) {
-                    dist = g.rec + int64_t(r) * g.rec_stride;
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) q[a] = P[a] - (b[a] << bs) + 32768;
-                    left = kn - k;
-                }
-            }
-        }
-        while (__any(left > 0)) {
-            if (left > 0) {
-                const int32_t p[3] = {q[0] >> 16, q[1] >> 16, q[2] >> 16};
-                const int32_t d = dist[cell_index(p, nc, ncc)];
-                int32_t adv = 1;
-                if (d == 0) {
-                    const int32_t fr[3] = {q[0] & 0xFFFF, q[1] & 0xFFFF, q[2] & 0xFFFF};
-                    if (on_sample(klo + kk, r, dist + g.dist_bytes, p, fr)) {
-                        live = false;
-                        adv = left;
-                    }
-                } else {
-                    adv = skip_steps(d, smax, inv_smax);
-                    adv = adv < left ? adv : left;
-                }
-                kk += adv;
-                left -= adv;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) q[a] += adv * s[a];
-            }
-            if (on_sync()) {
-                live = false;
-                left = 0;
-            }
-        }
-        if (live) {
-            const int32_t adv = kn - k;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) P[a] += adv * s[a];
-            k = kn;
-        }
-    }
 }
 
 }  // namespace snerg
