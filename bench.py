@@ -8,7 +8,8 @@ Headline (value): forward Mrays/s of the plain FP32 path on the 512^3 grid
 (B = 32, ~10.6% occupied procedural shell) for one 800x800 camera, with
 inputs resident in device memory; fps = value / 0.64.  Further legs, each
 timed the same way: the batched FP16-MFMA-MLP forward (1024^3 grid, 16
-cameras of mixed size in one persistent launch replayed from a HIP graph)
+cameras of mixed size in one launch replayed from a HIP graph, tiled or
+persistent as the autotuner finds faster)
 with its max-abs error against the FP64 oracle, the adjoint (8 views at
 800x800 on a float32 shadow of the 512^3 grid, forward + backward), the
 large case (64 x 1920x1080 in one launch, then 65,536-ray minibatch forward
@@ -143,6 +144,21 @@ def algorithmic_bytes(cnt):
     return 4 * cnt["blocks"] + cnt["inblock"] + 64 * cnt["active"] + 16 * cnt["rays"]
 
 
+def tune_launch(S, h, grid, m, carr, out, reps, tiles=None, persistent=None):
+    """Autotunes the FP16 graph launch in both launch modes (tiled wavefronts
+    issued by the hardware, or persistent workgroups pulling tiles from a
+    counter) and keeps the faster: (opts, tuning, ms, mode)."""
+    best = None
+    for mode, cands in (("tiles", tiles), ("persistent", persistent)):
+        opts = S.make_opts(fp16=True, persistent=(mode == "persistent"), graph=True)
+        t, ms = S.snerg_autotune(h, grid, m, carr, opts, out, reps=reps, candidates=cands)
+        log(f"  {mode}: {t} at {ms:.3f} ms")
+        if best is None or ms < best[2]:
+            best = (opts, t, ms, mode)
+    S.snerg_set_tuning(h, *best[1])
+    return best
+
+
 def leg_plain(args, torch, S, W, O):
     cfg = W.config("plain512")
     g, cams, mlp = cfg["grid"], cfg["cams"], cfg["mlp"]
@@ -187,11 +203,10 @@ def leg_batched(args, torch, S, W, O):
     n = sum(c.n_rays for c in cams)
     out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
     carr = S.make_cameras(cams)
-    opts = S.make_opts(fp16=True, persistent=True, graph=True)
     log(f"batched1024: {g.n_blocks} blocks, {len(cams)} cameras, {n} rays; autotuning")
-    best, best_ms = S.snerg_autotune(h, dg.struct(), m, carr, opts, out, reps=2)
-    log(f"batched1024: tuning {best} at {best_ms:.3f} ms")
     grid = dg.struct()
+    opts, best, best_ms, mode = tune_launch(S, h, grid, m, carr, out, 2)
+    log(f"batched1024: {mode} launch, tuning {best} at {best_ms:.3f} ms")
 
     def step():
         S.snerg_render(h, grid, m, carr, None, n, opts, out)
@@ -206,7 +221,7 @@ def leg_batched(args, torch, S, W, O):
     # 20 v_mfma_f32_16x16x16_f16 of 8,192 FLOP per 64 rays (K and N padded) are executed
     mlp_tflops = n * MLP_FLOP / (ms * 1e-3) / 1e12
     res = dict(ms=ms, rays=n, mrays=n / ms / 1e3, max_abs_err=err, err_sample=len(ids), tuning=list(best),
-               cpu_mrays=cpu_mrays, mlp_tflops=mlp_tflops, mfma_frac=mlp_tflops / FP16_PEAK_TFLOPS,
+               mode=mode, cpu_mrays=cpu_mrays, mlp_tflops=mlp_tflops, mfma_frac=mlp_tflops / FP16_PEAK_TFLOPS,
                mfma_tflops_executed=n / 64 * 20 * 8192 / (ms * 1e-3) / 1e12)
     log(f"batched1024: {ms:.3f} ms/batch, {res['mrays']:.1f} Mrays/s, fp16 max-abs err {err:.2e}; MLP "
         f"{mlp_tflops:.2f} TFLOP/s = {100 * res['mfma_frac']:.3f}% of the FP16 MFMA peak")
@@ -265,7 +280,8 @@ def leg_adjoint(args, torch, S, W, O):
 
 
 def leg_large(args, torch, S, W, O):
-    """64 x 1920x1080 forward in one persistent graph launch (FP16 MLP), then
+    """64 x 1920x1080 forward in one graph launch (FP16 MLP, tiled or persistent
+    as the autotuner finds faster), then
     forward + backward on random 65,536-ray minibatches over all 64 views
     (FP16 MLP forward and backward, float32 shadow of the grid): independent
     pixels, and whole 8x8 patches."""
@@ -278,11 +294,11 @@ def leg_large(args, torch, S, W, O):
     n = sum(c.n_rays for c in cams)
     out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
     carr = S.make_cameras(cams)
-    opts = S.make_opts(fp16=True, persistent=True, graph=True)
     log(f"large1024: {g.n_blocks} blocks ({g.meta['occupancy']:.3f}), {len(cams)} cameras, {n} rays")
-    best, _ = S.snerg_autotune(h, dg.struct(), m, carr, opts, out, reps=1,
-                               candidates=[(8, 8, 4, 8), (8, 8, 2, 8), (8, 8, 4, 4), (16, 4, 4, 8)])
     grid = dg.struct()
+    opts, best, _, mode = tune_launch(S, h, grid, m, carr, out, 1,
+                                      tiles=[(8, 8, 4, 8), (8, 8, 2, 8), (16, 4, 4, 8)],
+                                      persistent=[(8, 8, 4, 3), (8, 8, 4, 4), (8, 8, 2, 6), (8, 8, 4, 2)])
 
     def step():
         S.snerg_render(h, grid, m, carr, None, n, opts, out)
@@ -340,7 +356,7 @@ def leg_large(args, torch, S, W, O):
     it[0] = 0
     ms_step_p = time_launches(train_step, 8, 2, torch)
     ms_f_p = time_launches(fwd_only, 8, 2, torch)
-    res = dict(ms=ms, rays=n, mrays=n / ms / 1e3, max_abs_err=err, tuning=list(best), mb=mb, cpu_mrays=cpu_mrays,
+    res = dict(ms=ms, rays=n, mrays=n / ms / 1e3, max_abs_err=err, tuning=list(best), mode=mode, mb=mb, cpu_mrays=cpu_mrays,
                ms_train_step=ms_step, ms_mb_fwd=ms_f, bwd_mrays=mb / ms_b / 1e3,
                ms_train_step_patches=ms_step_p, ms_mb_fwd_patches=ms_f_p,
                bwd_mrays_patches=mb / max(ms_step_p - ms_f_p, 1e-6) / 1e3)
@@ -595,7 +611,7 @@ def main():
         legs_out["batched_fp16_1024"] = {"mrays": round(b["mrays"], 3), "ms": round(b["ms"], 4),
                                          "fps_800x800_equiv": round(b["mrays"] / 0.64, 2),
                                          "max_abs_err_vs_oracle": b["max_abs_err"], "err_sample": b["err_sample"],
-                                         "rays": b["rays"], "tuning": b["tuning"],
+                                         "rays": b["rays"], "tuning": b["tuning"], "launch": b["mode"],
                                          "cpu_oracle_mrays": round(b["cpu_mrays"], 4),
                                          "roofline_mfma": {"bound": "mfma", "achieved": round(b["mlp_tflops"], 3),
                                                            "peak": FP16_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -618,7 +634,7 @@ def main():
         legs_out["large_1024"] = {"mrays": round(b["mrays"], 3), "ms": round(b["ms"], 3),
                                   "fps_800x800_equiv": round(b["mrays"] / 0.64, 2),
                                   "max_abs_err_vs_oracle": b["max_abs_err"], "rays": b["rays"],
-                                  "tuning": b["tuning"], "minibatch": b["mb"],
+                                  "tuning": b["tuning"], "launch": b["mode"], "minibatch": b["mb"],
                                   "ms_minibatch_fwd_bwd": round(b["ms_train_step"], 4),
                                   "bwd_mrays": round(b["bwd_mrays"], 3), "cpu_oracle_mrays": round(b["cpu_mrays"], 4),
                                   "ms_minibatch_fwd_bwd_patches": round(b["ms_train_step_patches"], 4),

@@ -339,7 +339,10 @@ int snerg_get_tuning(snerg_handle *h, snerg_tuning *t);
 /*
  * Times each candidate launch shape (HIP events, `reps` renders after one
  * warm-up) for the given render call and keeps the fastest in the handle.
- * candidates: host [n_candidates] or NULL for the built-in search space.
+ * candidates: host [n_candidates] or NULL for the built-in search space
+ * (tiles 8x8, 16x4, 4x16 and 32x2; 1, 2 or 4 wavefronts per workgroup; with
+ * SNERG_FLAG_PERSISTENT also 2, 3, 4, 6 or 8 resident workgroups per CU).
+ * The launch mode itself (tiles or persistent) is the one opts selects.
  * out_rgba receives the last render.  best (host, nullable) receives the
  * winner and best_ms its time per render.  Synchronises `stream`.
  */

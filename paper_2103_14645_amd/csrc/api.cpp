@@ -776,11 +776,11 @@ int snerg_autotune(snerg_handle* h, const snerg_grid* grid, const float* mlp, co
     } else {
         const int shapes[4][2] = {{8, 8}, {16, 4}, {4, 16}, {32, 2}};
         const int wpgs[3] = {1, 2, 4};
-        const int gpcs[3] = {2, 4, 8};
+        const int gpcs[5] = {2, 3, 4, 6, 8};
         const bool persistent = (opts->flags & SNERG_FLAG_PERSISTENT) != 0;
         for (auto& sh : shapes)
             for (int w : wpgs)
-                for (int gi = 0; gi < (persistent ? 3 : 1); ++gi)
+                for (int gi = 0; gi < (persistent ? 5 : 1); ++gi)
                     cand.push_back(snerg_tuning{sh[0], sh[1], w, persistent ? gpcs[gi] : 8});
     }
     if (!h) return fail(SNERG_ERR_INVALID_ARG, "handle is NULL");
