@@ -436,14 +436,16 @@ __device__ __forceinline__ void march_ray_flat_sync(const GridArgs& g, const uin
     }
 }
 
-// Occupied macroblocks whose first sample on the ray's lattice lies in the
-// part [k0, k1] of the lattice indices inside the grid: the macroblock walk
-// of march_ray alone, without visiting samples and without early stop (a cost
-// estimate for scheduling, not part of any result).  Splitting [klo, khi]
-// into parts and adding their counts gives the ray's count exactly: a block
-// that a part starts in the middle of belongs to the part before.
-__host__ __device__ __forceinline__ int32_t occupied_blocks_on_ray(const GridArgs& g, const uint2* occ, const int64_t o[3],
-                                                          const int32_t s[3], int part, int n_parts) {
+// Samples of the ray inside occupied macroblocks, counted for the blocks
+// whose first sample on the ray's lattice lies in the part [k0, k1] of the
+// lattice indices inside the grid: the macroblock walk of march_ray alone,
+// without visiting samples and without early stop (a cost estimate for
+// scheduling, not part of any result).  A block is counted whole by the part
+// its first sample lies in, so adding the parts' counts gives the ray's
+// count exactly.
+__host__ __device__ __forceinline__ int32_t occupied_samples_on_ray(const GridArgs& g, const uint2* occ,
+                                                                   const int64_t o[3], const int32_t s[3], int part,
+                                                                   int n_parts) {
     const int bs = 16 + g.logB;
     const int64_t L = int64_t(g.N) << 16;
     int64_t klo, khi;
@@ -459,7 +461,8 @@ __host__ __device__ __forceinline__ int32_t occupied_blocks_on_ray(const GridArg
         inv[a] = sa != 0 ? 1.0f / float(sa) : 0.0f;
         P[a] = int32_t(o[a] + k0 * int64_t(s[a]));
     }
-    const int32_t kend = int32_t(k1 - k0);
+    const int32_t kend = int32_t(k1 - k0);       // the part's last sample, relative
+    const int32_t krest = int32_t(khi - k0);     // the ray's last sample, relative
     int32_t k = 0, count = 0;
     bool first = k0 > klo;
     while (k <= kend) {
@@ -476,7 +479,9 @@ __host__ __device__ __forceinline__ int32_t occupied_blocks_on_ray(const GridArg
                                   ((P[2] - s[2]) >> bs) != b[2]);
             first = false;
         }
-        count += int32_t(counted);
+        // the whole block up to the ray's end, also past the part's end
+        const int32_t n = (k + nstep) <= krest + 1 ? nstep : krest + 1 - k;
+        count += counted ? n : 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) P[a] += nstep * s[a];
         k += nstep;

@@ -245,11 +245,13 @@ __global__ __launch_bounds__(256) void k_trace(RenderArgs a) {
 // Heavy-first tile order.  A frame lasts as long as its slowest wavefronts
 // (tiles whose rays graze the surface and composite hundreds of samples);
 // issued late, they run on an emptying machine and set the frame time.
-// Tiles are therefore sorted by a cost class, the number of occupied
-// macroblocks on the tile's centre ray (capped at 15), and the render takes
-// them in decreasing class.  Pass 1: eight lanes per tile walk eighths of
-// its centre ray and add their counts into its class; the class histogram.  Pass 2: each workgroup reserves, per class, a
-// range after all tiles of higher classes and writes its tiles there.
+// Tiles are therefore sorted by a cost class, the number of the tile's
+// centre-ray samples that lie inside occupied macroblocks (before early
+// termination, in steps of N/16, capped at 15), and the render takes them
+// in decreasing class.  Pass 1: eight lanes per tile walk eighths of its
+// centre ray and add their counts into its class; the class histogram.
+// Pass 2: each workgroup reserves, per class, a range after all tiles of
+// higher classes and writes its tiles there.
 constexpr int kCostParts = 8;  // lanes per tile, each walking a part of the centre ray
 
 __global__ __launch_bounds__(256) void k_tile_cost(RenderArgs a, uint8_t* __restrict__ cls,
@@ -272,13 +274,16 @@ __global__ __launch_bounds__(256) void k_tile_cost(RenderArgs a, uint8_t* __rest
         int32_t sd[3];
         float d[3];
         ray_setup(c, a.grid.N, px, py, o, sd, d);
-        k = occupied_blocks_on_ray(a.grid, occ, o, sd, part, kCostParts);
+        k = occupied_samples_on_ray(a.grid, occ, o, sd, part, kCostParts);
     }
     // the parts of one tile are adjacent lanes of one wavefront
 #pragma unroll
     for (int m = 1; m < kCostParts; m <<= 1) k += __shfl_xor(k, m);
     if (t < a.total_tiles && part == 0) {
-        k = min(k, kCostClasses - 1);
+        // classes of N/16 samples: a ray crossing the whole grid has up to
+        // 2 sqrt(3) N samples, so rays with more than N samples inside
+        // occupied blocks share the top class
+        k = min(k / max(1, a.grid.N >> 4), kCostClasses - 1);
         cls[t] = uint8_t(k);
         atomicAdd(&hist[k], 1);
     }
