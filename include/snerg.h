@@ -354,11 +354,15 @@ int snerg_autotune(snerg_handle *h, const snerg_grid *grid, const float *mlp,
 /* ----------------------------------------------------------- measurement */
 
 /*
- * Kernel timing for measurement.  While enabled, every snerg_render
+ * Kernel timing for measurement.  While enabled, every on-th snerg_render
+ * call (on = 1: every call; the first call after enabling is timed)
  * records a pair of HIP events on its stream around its render kernel
  * alone (after the tile-order pre-pass; around the whole replay in graph
- * mode) into a ring that keeps the last 256 renders.  snerg_timing_enable
- * with on != 0 empties the ring; on = 0 stops recording.
+ * mode) into a ring that keeps the last 256 timed renders.  Each event
+ * pair costs the stream some microseconds, so timing a sample of the calls
+ * disturbs a run of back-to-back renders less.  snerg_timing_enable with
+ * on >= 1 empties the ring; on = 0 stops recording; on < 0 is
+ * SNERG_ERR_INVALID_ARG.
  * snerg_timing_read synchronises the recorded events and writes up to
  * `max` kernel times in milliseconds, oldest first, to ms (host), and the
  * number written to *n.

@@ -159,8 +159,11 @@ struct snerg_handle {
     float* d_bake = nullptr;  // baking scratch: per-block max density, visibility words, atlas map
     size_t bake_cap = 0;      // in floats
     int32_t* h_bake_count = nullptr;  // pinned: kept-block count read back by snerg_bake_cull
-    // kernel timing ring (measurement aid)
-    bool timing = false;
+    // kernel timing ring (measurement aid): every timing_every-th render
+    // call is timed (0: none); timing_now says whether the current one is
+    int32_t timing_every = 0;
+    int64_t timing_calls = 0;
+    bool timing_now = false;
     std::vector<hipEvent_t> t_start, t_stop;
     int64_t t_count = 0;
     snerg_tuning tuning = {8, 8, 4, 8};
@@ -252,11 +255,12 @@ constexpr int kTimingRing = 256;
 
 // Events around the render kernel when timing is enabled (no-ops otherwise).
 hipError_t timing_begin(snerg_handle* h, hipStream_t s) {
-    if (!h->timing) return hipSuccess;
+    h->timing_now = h->timing_every > 0 && h->timing_calls++ % h->timing_every == 0;
+    if (!h->timing_now) return hipSuccess;
     return hipEventRecord(h->t_start[size_t(h->t_count % kTimingRing)], s);
 }
 hipError_t timing_end(snerg_handle* h, hipStream_t s) {
-    if (!h->timing) return hipSuccess;
+    if (!h->timing_now) return hipSuccess;
     hipError_t e = hipEventRecord(h->t_stop[size_t(h->t_count % kTimingRing)], s);
     ++h->t_count;
     return e;
@@ -716,6 +720,7 @@ int snerg_bake_quantize(snerg_handle* h, int32_t N, int32_t B, const float* sigm
 }
 
 int snerg_timing_enable(snerg_handle* h, int32_t on) {
+    if (on < 0) return fail(SNERG_ERR_INVALID_ARG, "on must be >= 0 (0 off, n: every n-th render)");
     if (!h) return fail(SNERG_ERR_INVALID_ARG, "handle is NULL");
     if (on && h->t_start.empty()) {
         h->t_start.resize(kTimingRing, nullptr);
@@ -725,8 +730,12 @@ int snerg_timing_enable(snerg_handle* h, int32_t on) {
             HIP_TRY(hipEventCreate(&h->t_stop[size_t(i)]));
         }
     }
-    h->timing = on != 0;
-    if (on) h->t_count = 0;
+    h->timing_every = on;
+    h->timing_now = false;
+    if (on) {
+        h->t_count = 0;
+        h->timing_calls = 0;
+    }
     return SNERG_OK;
 }
 

@@ -238,7 +238,8 @@ def snerg_adam_step(handle, param, grad, m, v, n, lr, step, beta1=0.9, beta2=0.9
 
 
 def snerg_timing_enable(handle, on=True):
-    _check(lib().snerg_timing_enable(handle.h, int(bool(on))), "snerg_timing_enable")
+    """on: False/0 off, True/1 time every render call, n >= 1 every n-th."""
+    _check(lib().snerg_timing_enable(handle.h, int(on)), "snerg_timing_enable")
 
 
 def snerg_timing_read(handle, max_n=256):

@@ -258,6 +258,7 @@ def test_timing_entry_point_validation():
     n = ctypes.c_int32(0)
     buf = (ctypes.c_float * 4)()
     assert lib.snerg_timing_enable(None, 1) == S.SNERG_ERR_INVALID_ARG and "handle" in last_error()
+    assert lib.snerg_timing_enable(None, -1) == S.SNERG_ERR_INVALID_ARG and "on must be" in last_error()
     assert lib.snerg_timing_read(None, buf, 4, None) == S.SNERG_ERR_INVALID_ARG
     assert lib.snerg_timing_read(None, None, 4, ctypes.byref(n)) == S.SNERG_ERR_INVALID_ARG
     assert lib.snerg_timing_read(None, buf, -1, ctypes.byref(n)) == S.SNERG_ERR_INVALID_ARG

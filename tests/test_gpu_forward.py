@@ -198,7 +198,7 @@ def test_large1024_all_cameras_one_launch_sampled():
 
 
 def test_kernel_timing_ring():
-    say("kernel timing: one event pair per render, every launch mode")
+    say("kernel timing: one event pair per timed render, every launch mode, sampling stride")
     g, cams, mlp = tiny_case(64, 1)
     dg = device_grid(g)
     h = handle()
@@ -218,6 +218,13 @@ def test_kernel_timing_ring():
     assert len(S.snerg_timing_read(h)) == 4  # disabled: nothing more recorded
     S.snerg_timing_enable(h, True)
     assert S.snerg_timing_read(h) == []
+    # every 3rd call: calls 1, 4 and 7 of seven are timed, in every launch mode
+    S.snerg_timing_enable(h, 3)
+    for i in range(7):
+        kw = (dict(), dict(persistent=True), dict(persistent=True, graph=True))[i % 3]
+        S.snerg_render(h, dg.struct(), m, carr, None, n, S.make_opts(**kw), out)
+    ms = S.snerg_timing_read(h)
+    assert len(ms) == 3 and all(0.0 < t < 1000.0 for t in ms)
     S.snerg_timing_enable(h, False)
 
 
