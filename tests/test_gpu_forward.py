@@ -133,6 +133,9 @@ def test_fp16_mlp_error_report(name):
     say(f"  fp16 max_err={err.max():.3e} fp32 max_err={err32.max():.3e} near_threshold={flagged}")
     assert err.max() <= TOL_F16
     assert err32.max() <= TOL_F32
+    # the tiled graph launch (the one the batched benchmark keeps) gives the same bits
+    tiled = gpu_render(dg, mlp, cams, fp16=True, graph=True)
+    assert np.array_equal(tiled, frame)
 
 
 def test_float32_grid_forward():
