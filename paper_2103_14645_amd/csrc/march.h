@@ -295,7 +295,7 @@ __host__ __device__ __forceinline__ int32_t mul_s24(int32_t a, int32_t b) {
 struct FlatWalk {
     int32_t kc[3], F[3], Q[3];
     int32_t smax, lin, kend;
-    int32_t k;     // first relative sample of the current macroblock
+    int32_t k;     // first relative sample of the next macroblock to enter
     int32_t kk;    // relative sample at q
     int32_t left;  // samples of the current occupied macroblock from q on
     int32_t r;
