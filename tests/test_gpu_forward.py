@@ -117,6 +117,26 @@ def test_plain512_frame_sampled_rays():
     assert np.array_equal(cnt.cpu().numpy(), ocnt) and np.array_equal(vis.cpu().numpy(), ovis)
 
 
+def test_plain512_grid_other_cameras_sampled_rays():
+    # the headline grid from four more viewpoints (radii 1.3 to 3, one camera
+    # inside the bounding box's corner region, elevations -40 to 70 degrees),
+    # all cameras in one tiled launch: 6,000 sampled rays vs the oracle
+    cfg = W.config("plain512")
+    g, mlp = cfg["grid"], cfg["mlp"]
+    cams = [W.look_at(W.orbit_eye(r, el, a), 200, 150, fov)
+            for r, el, a, fov in ((1.3, -40.0, 0.4, 60.0), (2.0, 70.0, 2.1, 39.0), (3.0, 5.0, 4.0, 25.0),
+                                  (1.55, 20.0, 5.5, 90.0))]
+    n = sum(c.n_rays for c in cams)
+    say(f"plain512 grid, {len(cams)} other cameras, {n} rays")
+    dg = device_grid(g)
+    frame = gpu_render(dg, mlp, cams)
+    ids = np.sort(np.random.default_rng(17).choice(n, 6000, replace=False))
+    err, flagged = parity_error(frame[ids], oracle_variants(O.OracleGrid(g), mlp, cams, ids=ids))
+    say(f"  max_err={err.max():.3e} near_threshold={flagged} hit_frac={(frame[ids, 3] > 0).mean():.3f}")
+    assert err.max() <= TOL_F32
+    assert (frame[ids, 3] > 0).mean() > 0.2  # the views do see the shell
+
+
 @pytest.mark.parametrize("name", ["tiny", "batched1024"])
 def test_fp16_mlp_error_report(name):
     cfg = W.config(name)
