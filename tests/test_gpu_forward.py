@@ -117,6 +117,19 @@ def test_plain512_frame_sampled_rays():
     assert np.array_equal(cnt.cpu().numpy(), ocnt) and np.array_equal(vis.cpu().numpy(), ovis)
 
 
+def test_plain512_whole_frame_vs_oracle():
+    # every one of the 640,000 rays of the headline frame, as the benchmark
+    # renders it (tiled launch, heavy-first order), against the FP64 oracle
+    cfg = W.config("plain512")
+    g, cams, mlp = cfg["grid"], cfg["cams"], cfg["mlp"]
+    dg = device_grid(g)
+    frame = gpu_render(dg, mlp, cams)
+    say(f"plain512: whole frame, {frame.shape[0]} rays vs oracle")
+    err, flagged = parity_error(frame, oracle_variants(O.OracleGrid(g), mlp, cams))
+    say(f"  max_err={err.max():.3e} near_threshold={flagged}")
+    assert err.max() <= TOL_F32
+
+
 def test_plain512_grid_other_cameras_sampled_rays():
     # the headline grid from four more viewpoints (radii 1.3 to 3, one camera
     # inside the bounding box's corner region, elevations -40 to 70 degrees),
