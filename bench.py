@@ -393,6 +393,14 @@ def leg_nondeferred(args, torch, S, W, plain):
     res["mlp_off"] = dict(ms=ms_off, mrays=n / ms_off / 1e3, mlp_share_of_deferred_frame=1.0 - ms_off / plain["ms"])
     log(f"no view network: {ms_off:.3f} ms/frame; the deferred network is {100 * (1 - ms_off / plain['ms']):.1f}% "
         f"of the deferred frame")
+    # the WebGL viewer's render variants (Appendix A, Eq. 9): the nearest-voxel gate
+    # composites fewer samples; the partial un-premultiply rescales each pixel
+    for name, kw in (("nn_gate", dict(nn_gate=True)), ("unpremultiply", dict(unpremultiply=True))):
+        opts = S.make_opts(**kw)
+        ms = time_launches(lambda: S.snerg_render(h, grid, m, carr, None, n, opts, out), max(4, args.steps // 2), 2,
+                           torch)
+        res[name] = dict(ms=ms, mrays=n / ms / 1e3, vs_exact_frame=ms / plain["ms"])
+        log(f"variant {name}: {ms:.3f} ms/frame ({n / ms / 1e3:.1f} Mrays/s)")
     for name, fp16 in (("fp32", False), ("fp16_mfma", True)):
         opts = S.make_opts(fp16=fp16, per_sample_mlp=True)
         ms = time_launches(lambda: S.snerg_render(h, grid, m, carr, None, n, opts, out), max(4, args.steps // 2),
