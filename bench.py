@@ -370,7 +370,7 @@ def leg_large(args, torch, S, W, O):
 
 
 def leg_nondeferred(args, torch, S, W, plain):
-    """The performance ablation of Section 6 on the plain 512^3 frame: no
+    """The performance ablation of Section 7.1 on the plain 512^3 frame: no
     view network at all, and the view network on every composited sample
     rather than a single time per ray, in FP32 and on FP16 MFMA tiles; the
     deferral speed-up against the deferred FP32 frame and the per-sample
@@ -386,7 +386,7 @@ def leg_nondeferred(args, torch, S, W, plain):
     grid = dg.struct()
     active = plain["counters"]["active"]
     res = {}
-    # ablation row 1 of Section 6: no view-dependent network at all (diffuse colour only)
+    # ablation row 1 of Section 7.1: no view-dependent network at all (diffuse colour only)
     off = S.make_opts(mlp_on=False)
     ms_off = time_launches(lambda: S.snerg_render(h, grid, m, carr, None, n, off, out), max(4, args.steps // 2), 2,
                            torch)

@@ -103,7 +103,7 @@ extern "C" {
  * before the deferred MLP; forward only. */
 #define SNERG_FLAG_NN_GATE (1u << 4)
 #define SNERG_FLAG_UNPREMULTIPLY (1u << 5)
-/* Not deferred (the performance ablation of Section 6): the view network
+/* Not deferred (the performance ablation of Section 7.1): the view network
  * runs on every composited sample, on that sample's colour and features and
  * the ray direction, its residual added to the sample's colour before
  * compositing; nothing runs per pixel.  Forward only, without aux; with

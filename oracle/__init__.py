@@ -207,9 +207,10 @@ def render(og: OracleGrid, mlp, cams, ray_ids=None, bg=(1.0, 1.0, 1.0), t_stop=D
            early_stop=True, mlp_on=True, threads: int = 0, nn_gate=False, unpremultiply=False,
            per_sample_mlp=False):
     """Renders the given rays (all rays when ray_ids is None).  Returns a dict
-    with rgba [n,4], aux [n,9] (C_d, V, T, gate) and counters [n,5]
+    with rgba [n,4], aux [n,9] (C_d, V, T, gate) and counters [n,7]
     (macroblocks traversed, occupied macroblocks visited, in-block samples,
-    composited samples, stopping k or -1)."""
+    composited samples, stopping k or -1, and the sums of the composited
+    samples' k and k^2 modulo 2^32 as int32 bits)."""
     lib = _load()
     ids, n = _ids(ray_ids, cams)
     c = _cams(cams)
@@ -217,7 +218,7 @@ def render(og: OracleGrid, mlp, cams, ray_ids=None, bg=(1.0, 1.0, 1.0), t_stop=D
     p = _mlp_vec(mlp)
     rgba = np.zeros((n, 4), np.float64)
     aux = np.zeros((n, 9), np.float64)
-    cnt = np.zeros((n, 5), np.int32)
+    cnt = np.zeros((n, 7), np.int32)
     _check(lib.orc_render(ctypes.byref(og.struct), _ptr(p), c, len(cams), _ptr(ids), n, ctypes.byref(o),
                           rgba.ctypes.data, aux.ctypes.data, cnt.ctypes.data, int(threads)), "render")
     return dict(rgba=rgba, aux=aux, counters=cnt)

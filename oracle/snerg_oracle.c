@@ -359,6 +359,8 @@ typedef struct {
     int32_t inblock_samples;  /* samples inside occupied macroblocks */
     int32_t active_samples;   /* samples composited */
     int32_t term_k;           /* k of the sample that stopped the ray, -1 if none */
+    uint32_t k_sum;           /* sum of the composited samples' k, modulo 2^32 */
+    uint32_t k_sq_sum;        /* sum of their k^2, modulo 2^32 */
 } ray_counters;
 
 typedef struct {
@@ -397,7 +399,7 @@ static int march_ray(const orc_grid *g, const double *mlp, const orc_camera *cam
 
     comp_state st;
     comp_init(&st);
-    ray_counters cnt = {0, 0, 0, 0, -1};
+    ray_counters cnt = {0, 0, 0, 0, -1, 0u, 0u};
     int64_t prev_blk = -1, prev_vis = -1;
     int seen_inside = 0;
     int32_t nv = 0;
@@ -432,6 +434,8 @@ static int march_ray(const orc_grid *g, const double *mlp, const orc_camera *cam
         double smp[8];
         if (!sample_point(g, P, smp, NULL, NULL)) continue;
         cnt.active_samples++;
+        cnt.k_sum += (uint32_t)k;
+        cnt.k_sq_sum += (uint32_t)k * (uint32_t)k;
         if (op->per_sample_mlp && op->mlp_on && mlp) {
             /* the network of Eq. 7 on this sample's own colour and features
              * (as NeRF queries its MLP at every sample), its residual added
@@ -520,9 +524,11 @@ static int set_threads(int32_t n_threads)
 /*
  * Renders rays ray_ids[0..n_rays) (all rays of all cameras when ray_ids is
  * NULL; then n_rays must equal their total).  rgba [n][4]; aux (nullable)
- * [n][9] = C_d, V, T, gate; counters (nullable) [n][5] = macroblocks
+ * [n][9] = C_d, V, T, gate; counters (nullable) [n][7] = macroblocks
  * traversed, occupied macroblocks visited, samples inside occupied
- * macroblocks, composited samples, stopping k (-1 if none).
+ * macroblocks, composited samples, stopping k (-1 if none), and the sums of
+ * the composited samples' k and k^2 modulo 2^32 (stored as int32 bits),
+ * which name the set of composited samples, not just its size.
  */
 int orc_render(const orc_grid *g, const double *mlp, const orc_camera *cams, int32_t n_cams,
                const int64_t *ray_ids, int64_t n_rays, const orc_opts *op, double *rgba, double *aux,
@@ -550,12 +556,14 @@ int orc_render(const orc_grid *g, const double *mlp, const orc_camera *cams, int
         memcpy(rgba + 4 * i, res.rgba, sizeof res.rgba);
         if (aux) memcpy(aux + 9 * i, res.aux, sizeof res.aux);
         if (counters) {
-            int32_t *c = counters + 5 * i;
+            int32_t *c = counters + 7 * i;
             c[0] = res.cnt.blocks_traversed;
             c[1] = res.cnt.blocks_occupied;
             c[2] = res.cnt.inblock_samples;
             c[3] = res.cnt.active_samples;
             c[4] = res.cnt.term_k;
+            c[5] = (int32_t)res.cnt.k_sum;
+            c[6] = (int32_t)res.cnt.k_sq_sum;
         }
     }
     return err;

@@ -1,4 +1,4 @@
-// The non-deferred render (the performance ablation of Section 6): the
+// The non-deferred render (the performance ablation of Section 7.1): the
 // view-dependent network of Eq. 7 runs on every composited sample, with that
 // sample's own colour and features and the ray direction, and its residual
 // is added to the sample's colour before compositing, as NeRF queries its

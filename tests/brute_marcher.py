@@ -61,7 +61,12 @@ def _mlp(mlp, C, V, dirs):
 def march(grid, lattice, mlp, values=None, bg=(1.0, 1.0, 1.0), t_stop=1e-3, early_stop=True,
           mlp_on=True, sigma_scale=50.0, nn_gate=False, unpremultiply=False, per_sample_mlp=False):
     """lattice: (o [n,3], s [n,3], d [n,3]) per ray.  Returns rgba [n,4], gate [n],
-    visits (list of lists of linear macroblock indices) and counts of composited samples."""
+    visits (list of lists of linear macroblock indices), counts of composited
+    samples and counters [n,7]: macroblocks traversed (runs of equal
+    consecutive macroblocks over the inside samples up to the stop), occupied
+    macroblocks visited, samples in occupied macroblocks up to the stop,
+    composited samples, the stopping k (-1 if none), and the sums of the
+    composited k and k^2 modulo 2^32 (as int32 bits)."""
     N, B = grid.N, grid.B
     G = N // B
     Dn, Rn, Fn, occ = dense_arrays(grid, values)
@@ -137,7 +142,17 @@ def march(grid, lattice, mlp, values=None, bg=(1.0, 1.0, 1.0), t_stop=1e-3, earl
     rgb = C + T[:, None] * np.asarray(bg)[None, :] + R
     rgba = np.concatenate([rgb, (1.0 - T)[:, None]], axis=1)
 
+    # per-ray counters, each from its own definition: the samples up to the
+    # stopping one (all inside samples without a stop) ...
+    upto = inside & (k[None, :] <= first[:, None])
+    # ... their macroblocks, counted once per run of equal consecutive blocks
+    runs = upto[:, :1].sum(axis=1) + (upto[:, 1:] & ~upto[:, :-1]).sum(axis=1) + \
+        (upto[:, 1:] & upto[:, :-1] & (lin_blk[:, 1:] != lin_blk[:, :-1])).sum(axis=1)
     visit_mask = blk_occ & (k[None, :] <= first[:, None])
+    stop_k = np.where(first <= kmax, first, -1)
+    kk = np.where(use, k[None, :], 0).astype(np.uint64)
+    ksum = (kk.sum(axis=1) % (1 << 32)).astype(np.uint32).view(np.int32)
+    ksq = ((kk * kk).sum(axis=1) % (1 << 32)).astype(np.uint32).view(np.int32)
     visits = []
     for r in range(n):
         seq = lin_blk[r][visit_mask[r]]
@@ -146,4 +161,6 @@ def march(grid, lattice, mlp, values=None, bg=(1.0, 1.0, 1.0), t_stop=1e-3, earl
             visits.append([int(v) for v in seq[keep_idx]])
         else:
             visits.append([])
-    return dict(rgba=rgba, gate=gate, visits=visits, n_used=use.sum(axis=1))
+    counters = np.stack([runs, [len(v) for v in visits], visit_mask.sum(axis=1), use.sum(axis=1), stop_k,
+                         ksum, ksq], axis=1).astype(np.int64)
+    return dict(rgba=rgba, gate=gate, visits=visits, n_used=use.sum(axis=1), counters=counters)

@@ -56,11 +56,11 @@ def test_nn_gate_counters_bit_exact(seed):
                                        max_visits=64)
         torch.cuda.synchronize()
         og = O.OracleGrid(g)
-        octr = O.render(og, None, cams, early_stop=early, mlp_on=False, nn_gate=True)["counters"]
+        octr = O.render(og, None, cams, early_stop=early, mlp_on=False, nn_gate=True)["counters"][:, :5]
         ovis, ocnt = O.trace_visits(og, cams, early_stop=early, max_visits=64, nn_gate=True)
         same = np.ones(len(octr), bool)
         if early:
-            alt = [O.render(og, None, cams, early_stop=True, mlp_on=False, nn_gate=True, t_stop=1e-3 * f)["counters"]
+            alt = [O.render(og, None, cams, early_stop=True, mlp_on=False, nn_gate=True, t_stop=1e-3 * f)["counters"][:, :5]
                    for f in (1 - 1e-5, 1 + 1e-5)]
             same = np.all(octr == alt[0], axis=1) & np.all(octr == alt[1], axis=1)
         ctr, cnt, vis = ctr.cpu().numpy(), cnt.cpu().numpy(), vis.cpu().numpy()

@@ -405,6 +405,8 @@ def test_oracle_matches_brute_force_dense_marcher(seed, n_occ, early):
     assert np.max(np.abs(r["rgba"] - b["rgba"])) < 1e-12
     assert np.array_equal(r["aux"][:, 8] != 0, b["gate"])
     assert np.array_equal(r["counters"][:, 3], b["n_used"])
+    # every counter, including the set of composited sample indices
+    assert np.array_equal(r["counters"].astype(np.int64), b["counters"])
     vis, cnt = O.trace_visits(og, [cam], early_stop=early)
     for i in range(cam.n_rays):
         assert list(vis[i, :cnt[i]]) == b["visits"][i]
@@ -442,6 +444,7 @@ def test_variants_match_brute_force(seed, n_occ, early):
         b = brute_marcher.march(g, lat, mlp, bg=(0.3, 0.6, 0.9), early_stop=early, **kw)
         assert np.max(np.abs(r["rgba"] - b["rgba"])) < 1e-12, kw
         assert np.array_equal(r["counters"][:, 3], b["n_used"]), kw
+        assert np.array_equal(r["counters"].astype(np.int64), b["counters"]), kw
     exact = O.render(og, mlp, [cam], early_stop=False)["counters"][:, 3]
     gated = O.render(og, mlp, [cam], early_stop=False, nn_gate=True)["counters"][:, 3]
     assert np.all(gated <= exact) and np.any(gated < exact)   # a strict subset of the samples
