@@ -226,6 +226,22 @@ int snerg_render_backward(snerg_handle *h, const snerg_grid *grid, const float *
                           float *grad_rgb, float *grad_feat, void *stream);
 
 /*
+ * snerg_render that also reports, per ray, what the render kernel's own
+ * march did (the samples of Section 5.2 and the per-sample accounting of
+ * Appendix A), for verification and measurement: the same kernel code and
+ * launch modes, compiled with counting.  counters: device int32
+ * [n_rays][7] = macroblocks entered, occupied macroblocks among them,
+ * samples inside occupied macroblocks (up to and including the stopping
+ * sample), composited samples, the stopping k (-1 if none), and the sums of
+ * the composited samples' k and k^2 modulo 2^32 (as int32 bits).  Other
+ * arguments and results as snerg_render; SNERG_FLAG_PER_SAMPLE_MLP is
+ * SNERG_ERR_UNSUPPORTED.
+ */
+int snerg_render_counted(snerg_handle *h, const snerg_grid *grid, const float *mlp, const snerg_camera *cams,
+                         int32_t n_cams, const int64_t *ray_ids, int64_t n_rays, const snerg_opts *opts,
+                         float *out_rgba, float *aux, int32_t *counters, void *stream);
+
+/*
  * Occupied macroblocks each ray visits in order (linear indirection index,
  * consecutive repeats collapsed), up to max_visits per ray, with the same
  * march and stopping rule as snerg_render.  visits: device int32

@@ -268,7 +268,8 @@ hipError_t timing_end(snerg_handle* h, hipStream_t s) {
 
 int render_impl(snerg_handle* h, const snerg_grid* grid, const float* mlp, const snerg_camera* cams,
                 int32_t n_cams, const int64_t* ray_ids, int64_t n_rays, const snerg_opts* opts,
-                float* out_rgba, float* aux, hipStream_t s, const snerg_tuning& tu) {
+                float* out_rgba, float* aux, hipStream_t s, const snerg_tuning& tu,
+                int32_t* counters = nullptr) {
     RenderArgs a;
     std::memset(&a, 0, sizeof a);
     int64_t total_tiles = 0;
@@ -287,6 +288,7 @@ int render_impl(snerg_handle* h, const snerg_grid* grid, const float* mlp, const
     a.tile_counter = h->d_counter;
     a.out = out_rgba;
     a.aux = aux;
+    a.counters = counters;
     const int vt = grid->dtype == SNERG_F32 ? 1 : 0;
     const int mlp_mode = !opts->mlp_on ? kMlpOff : ((opts->flags & SNERG_FLAG_MLP_FP16) ? kMlpF16 : kMlpF32);
     const int wpg = tu.waves_per_group;
@@ -454,6 +456,22 @@ int snerg_render(snerg_handle* h, const snerg_grid* grid, const float* mlp, cons
     if (n_rays == 0) return SNERG_OK;
     return render_impl(h, grid, mlp, cams, n_cams, ray_ids, n_rays, opts, out_rgba, aux,
                        static_cast<hipStream_t>(stream), h->tuning);
+}
+
+int snerg_render_counted(snerg_handle* h, const snerg_grid* grid, const float* mlp, const snerg_camera* cams,
+                         int32_t n_cams, const int64_t* ray_ids, int64_t n_rays, const snerg_opts* opts,
+                         float* out_rgba, float* aux, int32_t* counters, void* stream) {
+    int64_t total = 0;
+    if (n_rays < 0) return fail(SNERG_ERR_INVALID_ARG, "n_rays must be >= 0");
+    int rc = common_render_checks(grid, mlp, true, cams, n_cams, ray_ids, n_rays, opts, &total);
+    if (rc) return rc;
+    if (!out_rgba || !counters) return fail(SNERG_ERR_INVALID_ARG, "out_rgba/counters is NULL");
+    if (opts->flags & SNERG_FLAG_PER_SAMPLE_MLP)
+        return fail(SNERG_ERR_UNSUPPORTED, "no counted render with SNERG_FLAG_PER_SAMPLE_MLP");
+    if (!h) return fail(SNERG_ERR_INVALID_ARG, "handle is NULL");
+    if (n_rays == 0) return SNERG_OK;
+    return render_impl(h, grid, mlp, cams, n_cams, ray_ids, n_rays, opts, out_rgba, aux,
+                       static_cast<hipStream_t>(stream), h->tuning, counters);
 }
 
 int snerg_trace_visits(snerg_handle* h, const snerg_grid* grid, const snerg_camera* cams, int32_t n_cams,

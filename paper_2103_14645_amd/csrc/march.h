@@ -292,6 +292,14 @@ __host__ __device__ __forceinline__ int32_t mul_s24(int32_t a, int32_t b) {
 // kc_a + Q_a + 1, whichever is the first to satisfy the inequality.  The
 // next macroblock starts at min_a kc_a, as in march_ray, and every axis
 // whose kc_a equals it changes macroblock there.
+// Counting hooks of FlatWalk::trip: block(occupied) on every macroblock the
+// walk enters, inblock(n) when it passes n samples inside an occupied one
+// (the sample it takes, or the cells it skips).  NoCount compiles to nothing.
+struct NoCount {
+    __host__ __device__ __forceinline__ void block(bool) {}
+    __host__ __device__ __forceinline__ void inblock(int32_t) {}
+};
+
 struct FlatWalk {
     int32_t kc[3], F[3], Q[3];
     int32_t smax, lin, kend;
@@ -350,6 +358,13 @@ struct FlatWalk {
     template <typename OnSample>
     __host__ __device__ __forceinline__ bool trip(const GridArgs& g, const uint2* occ, const int32_t s[3],
                                                   OnSample&& on_sample) {
+        NoCount nc;
+        return trip(g, occ, s, on_sample, nc);
+    }
+
+    template <typename OnSample, typename Count>
+    __host__ __device__ __forceinline__ bool trip(const GridArgs& g, const uint2* occ, const int32_t s[3],
+                                                  OnSample&& on_sample, Count& cnt) {
         const int bs = 16 + g.logB;
         const int32_t W = int32_t(1) << bs;
         const uint32_t nc = uint32_t(g.Bc), ncc = nc * nc;
@@ -367,6 +382,7 @@ struct FlatWalk {
                 kn = kn < kc[2] ? kn : kc[2];
                 kn = kn < kend + 1 ? kn : kend + 1;
                 r = block_rank(occ, lin, g.n_blocks);
+                cnt.block(r >= 0);
                 if (r >= 0) {
                     dist = g.rec + int64_t(r) * g.rec_stride;
                     // Q16 position of sample k inside the macroblock, + 2^15 for the padding
@@ -401,6 +417,7 @@ struct FlatWalk {
                 adv = skip_steps(d, smax, inv_smax);
                 adv = adv < left ? adv : left;
             }
+            cnt.inblock(adv);
             kk += adv;
             left -= adv;
 #pragma unroll
@@ -410,12 +427,19 @@ struct FlatWalk {
     }
 };
 
+template <typename OnSample, typename Count>
+__host__ __device__ __forceinline__ void march_ray_flat(const GridArgs& g, const uint2* occ, const int64_t o[3],
+                                                        const int32_t s[3], OnSample&& on_sample, Count& cnt) {
+    FlatWalk w;
+    bool live = w.init(g, o, s);
+    while (live) live = w.trip(g, occ, s, on_sample, cnt);
+}
+
 template <typename OnSample>
 __host__ __device__ __forceinline__ void march_ray_flat(const GridArgs& g, const uint2* occ, const int64_t o[3],
                                                         const int32_t s[3], OnSample&& on_sample) {
-    FlatWalk w;
-    bool live = w.init(g, o, s);
-    while (live) live = w.trip(g, occ, s, on_sample);
+    NoCount nc;
+    march_ray_flat(g, occ, o, s, on_sample, nc);
 }
 
 // march_ray_flat made convergent across the wavefront: every live lane

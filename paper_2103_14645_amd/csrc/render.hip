@@ -29,9 +29,22 @@ __device__ __forceinline__ void composite(RayAccum& st, const Sample& smp, float
     st.gate = true;
 }
 
-template <int VT>
+// Per-ray counters of the render's own walk (the counted launch): the
+// march's FlatWalk hooks count macroblocks and in-block samples, the sample
+// callback the composited samples, their indices and the stop.
+struct RayCount {
+    int32_t blocks, occupied, in_block, active, stop_k;
+    uint32_t k_sum, k_sq;
+    __device__ __forceinline__ void block(bool occ) {
+        ++blocks;
+        occupied += occ ? 1 : 0;
+    }
+    __device__ __forceinline__ void inblock(int32_t n) { in_block += n; }
+};
+
+template <int VT, bool COUNT>
 __device__ __forceinline__ void march_composite(const RenderArgs& a, const uint2* occ, const int64_t o[3],
-                                                const int32_t s[3], RayAccum& st) {
+                                                const int32_t s[3], RayAccum& st, RayCount& rc) {
     const GridArgs& g = a.grid;
     const float cs = VT == 0 ? (1.0f / 255.0f) : 1.0f;
     const float kx = g.sigma_scale * cs / float(g.N);
@@ -43,9 +56,7 @@ __device__ __forceinline__ void march_composite(const RenderArgs& a, const uint2
     const uint8_t* cached = nullptr;
     Corners8 cn;
     const uint32_t nb = uint32_t(g.Bp), nbb = nb * nb;
-    march_ray_flat(
-        g, occ, o, s,
-        [&](int64_t, int32_t, const uint8_t* vox, const int32_t p[3], const int32_t fr[3]) {
+    auto on_sample = [&](int64_t k, int32_t, const uint8_t* vox, const int32_t p[3], const int32_t fr[3]) {
             Sample smp;
             if (VT == 0) {
                 const uint8_t* cell = vox + (uint64_t(cell_index(p, nb, nbb)) << 3);
@@ -60,8 +71,21 @@ __device__ __forceinline__ void march_composite(const RenderArgs& a, const uint2
             }
             if (!smp.active) return false;
             composite(st, smp, kx, cs);
-            return early && st.T < t_stop;
-        });
+            const bool stop = early && st.T < t_stop;
+            if (COUNT) {
+                const uint32_t ku = uint32_t(k);
+                ++rc.active;
+                rc.k_sum += ku;
+                rc.k_sq += ku * ku;
+                if (stop) rc.stop_k = int32_t(k);
+            }
+            return stop;
+        };
+    if (COUNT) {
+        march_ray_flat(g, occ, o, s, on_sample, rc);
+    } else {
+        march_ray_flat(g, occ, o, s, on_sample);
+    }
 }
 
 // The wavefront's tile or first ray index is the same in every lane; saying
@@ -94,10 +118,11 @@ __device__ __forceinline__ bool tile_pixel(const RenderArgs& a, int64_t t, int l
     return px < c.W && py < c.H;
 }
 
-template <int VT, int MLP>
+template <int VT, int MLP, bool COUNT>
 __device__ __forceinline__ void render_ray(const RenderArgs& a, const uint2* occ, bool valid, int ci, int px,
                                            int py, int64_t out_idx) {
     RayAccum st = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, 1.0f, false};
+    RayCount rc = {0, 0, 0, 0, -1, 0u, 0u};
     float d[3] = {0.f, 0.f, 1.f};
     if (valid) {
         int64_t o[3];
@@ -106,7 +131,7 @@ __device__ __forceinline__ void render_ray(const RenderArgs& a, const uint2* occ
         // keep the direction as three floats from here on (left alone, the
         // compiler carries its FP64 form through the march)
         asm volatile("" : "+v"(d[0]), "+v"(d[1]), "+v"(d[2]));
-        march_composite<VT>(a, occ, o, s, st);
+        march_composite<VT, COUNT>(a, occ, o, s, st, rc);
         if (a.opts.unpremultiply) {
             // Eq. 9: saturate alpha above 2/3, keep soft edges below
             const float al = 1.0f - st.T;
@@ -139,13 +164,24 @@ __device__ __forceinline__ void render_ray(const RenderArgs& a, const uint2* occ
             ax[0] = make_float4(st.C[0], st.C[1], st.C[2], st.V[0]);
             ax[1] = make_float4(st.V[1], st.V[2], st.V[3], st.gate ? st.T : -1.0f);
         }
+        if (COUNT) {
+            int32_t* c = a.counters + 7 * out_idx;
+            c[0] = rc.blocks;
+            c[1] = rc.occupied;
+            c[2] = rc.in_block;
+            c[3] = rc.active;
+            c[4] = rc.stop_k;
+            c[5] = int32_t(rc.k_sum);
+            c[6] = int32_t(rc.k_sq);
+        }
     }
 }
 
 // PERSIST selects the persistent kernel (a loop over the global tile queue);
 // the other kernel serves the one-wavefront-per-tile and ray-list launches.
 // They are separate kernels so that each gets its own register allocation.
-template <int VT, int MLP, bool PERSIST>
+// COUNT: the counted launch, which also writes each ray's march counters.
+template <int VT, int MLP, bool PERSIST, bool COUNT>
 __global__ __launch_bounds__(256) void k_render(RenderArgs a) {
     const uint2* occ = stage_occupancy(a.grid);
     const int lane = threadIdx.x & 63;
@@ -180,7 +216,7 @@ __global__ __launch_bounds__(256) void k_render(RenderArgs a) {
             if (t >= a.total_tiles) break;  // wave-uniform; every wave reaches it
             valid = tile_pixel(a, a.tile_order ? int64_t(a.tile_order[t]) : t, lane, ci, px, py, out_idx);
         }
-        render_ray<VT, MLP>(a, occ, valid, ci, px, py, out_idx);
+        render_ray<VT, MLP, COUNT>(a, occ, valid, ci, px, py, out_idx);
         if (!PERSIST) break;
     }
 }
@@ -346,10 +382,14 @@ static hipError_t launch_render_t(const RenderArgs& a, int wpg, int n_groups, hi
     else blocks = unsigned(n_groups);
     if (blocks == 0) return hipSuccess;
     const size_t lds = size_t(a.grid.n_words) * sizeof(uint2);
-    if (a.mode == kModePersistent)
-        hipLaunchKernelGGL((k_render<VT, MLP, true>), dim3(blocks), dim3(threads), lds, s, a);
-    else
-        hipLaunchKernelGGL((k_render<VT, MLP, false>), dim3(blocks), dim3(threads), lds, s, a);
+    const bool count = a.counters != nullptr;
+    if (a.mode == kModePersistent) {
+        if (count) hipLaunchKernelGGL((k_render<VT, MLP, true, true>), dim3(blocks), dim3(threads), lds, s, a);
+        else hipLaunchKernelGGL((k_render<VT, MLP, true, false>), dim3(blocks), dim3(threads), lds, s, a);
+    } else {
+        if (count) hipLaunchKernelGGL((k_render<VT, MLP, false, true>), dim3(blocks), dim3(threads), lds, s, a);
+        else hipLaunchKernelGGL((k_render<VT, MLP, false, false>), dim3(blocks), dim3(threads), lds, s, a);
+    }
     return hipGetLastError();
 }
 

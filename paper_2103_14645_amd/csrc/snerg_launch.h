@@ -36,7 +36,7 @@ struct RenderArgs {
     int32_t* visits;
     int32_t max_visits;
     int32_t* counts;
-    int32_t* counters;
+    int32_t* counters;       // trace: [n][5]; counted render: [n][7] (null: the plain render)
 };
 
 struct BackwardArgs {

@@ -5,7 +5,7 @@ kernels.  PyTorch supplies device memory (tensors) and the stream.  The
 entry points keep the C names:
 
     snerg_packed_size, snerg_pack_grid, snerg_render, snerg_render_backward,
-    snerg_trace_visits, snerg_set_tuning, snerg_get_tuning, snerg_autotune
+    snerg_render_counted, snerg_trace_visits, snerg_set_tuning, snerg_get_tuning, snerg_autotune
 
 plus small conveniences (Handle, DeviceGrid, render) that allocate the
 output tensors.  There is no fallback: if the library is missing or a call
@@ -105,6 +105,7 @@ def lib():
             "snerg_pack_grid": [_P, i32, i32, i32, i32, _P, _P, _P, _P, _P, sz, _P],
             "snerg_render": [_P, _P, _P, _P, i32, _P, i64, _P, _P, _P, _P],
             "snerg_render_backward": [_P, _P, _P, _P, i32, _P, i64, _P, _P, _P, _P, _P, _P, _P, _P],
+            "snerg_render_counted": [_P, _P, _P, _P, i32, _P, i64, _P, _P, _P, _P, _P],
             "snerg_trace_visits": [_P, _P, _P, i32, _P, i64, _P, i32, _P, _P, _P, _P],
             "snerg_set_tuning": [_P, _P],
             "snerg_get_tuning": [_P, _P],
@@ -129,7 +130,7 @@ def lib():
 
 
 EXPORTED = ["snerg_create", "snerg_destroy", "snerg_status_string", "snerg_last_error", "snerg_packed_size",
-            "snerg_pack_grid", "snerg_render", "snerg_render_backward", "snerg_trace_visits",
+            "snerg_pack_grid", "snerg_render", "snerg_render_backward", "snerg_render_counted", "snerg_trace_visits",
             "snerg_set_tuning", "snerg_get_tuning", "snerg_autotune", "snerg_loss_mse", "snerg_adam_step",
             "snerg_bake_cull", "snerg_bake_quantize", "snerg_timing_enable", "snerg_timing_read"]
 
@@ -216,6 +217,13 @@ def snerg_render(handle, grid: snerg_grid, mlp, cams, ray_ids, n_rays, opts, out
     _check(lib().snerg_render(handle.h, ctypes.byref(grid), _ptr(mlp), cams, len(cams), _ptr(ray_ids),
                               int(n_rays), ctypes.byref(opts), _ptr(out_rgba), _ptr(aux), _stream(stream)),
            "snerg_render")
+
+
+def snerg_render_counted(handle, grid: snerg_grid, mlp, cams, ray_ids, n_rays, opts, out_rgba, aux, counters,
+                         stream=None):
+    _check(lib().snerg_render_counted(handle.h, ctypes.byref(grid), _ptr(mlp), cams, len(cams), _ptr(ray_ids),
+                                      int(n_rays), ctypes.byref(opts), _ptr(out_rgba), _ptr(aux), _ptr(counters),
+                                      _stream(stream)), "snerg_render_counted")
 
 
 def snerg_render_backward(handle, grid: snerg_grid, mlp, cams, ray_ids, n_rays, opts, aux, grad_rgba,
@@ -354,6 +362,18 @@ def render(handle, dgrid: DeviceGrid, mlp, cams, ray_ids=None, opts=None, want_a
     aux = torch.empty((n, 8), dtype=torch.float32, device=dev) if want_aux else None
     snerg_render(handle, dgrid.struct(), mlp, carr, ray_ids, n, opts, out, aux, stream)
     return (out, aux) if want_aux else out
+
+
+def render_counted(handle, dgrid: DeviceGrid, mlp, cams, ray_ids=None, opts=None, stream=None):
+    """snerg_render_counted with allocated outputs: (rgba [n,4], counters [n,7] int32)."""
+    opts = opts or make_opts()
+    carr = make_cameras(cams)
+    n = int(ray_ids.numel()) if ray_ids is not None else sum(int(c.W) * int(c.H) for c in cams)
+    dev = dgrid.packed.device
+    out = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    counters = torch.full((n, 7), -7, dtype=torch.int32, device=dev)
+    snerg_render_counted(handle, dgrid.struct(), mlp, carr, ray_ids, n, opts, out, None, counters, stream)
+    return out, counters
 
 
 def trace_visits(handle, dgrid: DeviceGrid, cams, ray_ids=None, opts=None, max_visits=256, stream=None):
