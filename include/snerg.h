@@ -226,6 +226,24 @@ int snerg_render_backward(snerg_handle *h, const snerg_grid *grid, const float *
                           float *grad_rgb, float *grad_feat, void *stream);
 
 /*
+ * snerg_render for callers that cannot allocate device memory (code under
+ * HIP stream capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results, with every scratch buffer (camera table,
+ * tile order, tile counter) in a fixed 16 MiB device array that the library
+ * holds on each GPU it runs on until the process ends; it calls no
+ * allocating routine.  Limits: at most 1024 cameras and, without ray_ids, at
+ * most 3,327,488 tiles of 64 pixels (about 212 M rays) per call, else
+ * SNERG_ERR_WORKSPACE; SNERG_FLAG_GRAPH is SNERG_ERR_UNSUPPORTED (graph
+ * instantiation allocates).  All calls on one GPU share the array: calls
+ * whose work overlaps on that GPU (other streams, other host threads) race
+ * and must be ordered by the caller.  Arguments and results as snerg_render;
+ * the handle supplies the launch shape.
+ */
+int snerg_render_noalloc(snerg_handle *h, const snerg_grid *grid, const float *mlp, const snerg_camera *cams,
+                         int32_t n_cams, const int64_t *ray_ids, int64_t n_rays, const snerg_opts *opts,
+                         float *out_rgba, float *aux, void *stream);
+
+/*
  * snerg_render that also reports, per ray, what the render kernel's own
  * march did (the samples of Section 5.2 and the per-sample accounting of
  * Appendix A), for verification and measurement: the same kernel code and

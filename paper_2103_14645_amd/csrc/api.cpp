@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -363,6 +364,57 @@ int render_impl(snerg_handle* h, const snerg_grid* grid, const float* mlp, const
     return SNERG_OK;
 }
 
+// ------------------------------------------------ allocation-free render
+
+// Every scratch buffer of the render path in one fixed device array, for
+// callers that cannot allocate (snerg_render_noalloc).  Layout: tile-order
+// class counters (64 int32), the persistent launch's tile counter, the
+// camera table (kNoAllocMaxCams entries), the tile order (int32 per tile) and
+// the tile classes (one byte per tile).  Each GPU holds its own copy; its
+// address comes from hipGetSymbolAddress with that GPU current.
+constexpr size_t kScratchBytes = size_t(16) << 20;
+constexpr int32_t kNoAllocMaxCams = 1024;
+constexpr size_t kScrCounts = 0;
+constexpr size_t kScrCounter = 256;
+constexpr size_t kScrCams = 512;
+constexpr size_t kScrOrder = (kScrCams + size_t(kNoAllocMaxCams) * sizeof(DevCamera) + 255) & ~size_t(255);
+constexpr int64_t kNoAllocMaxTiles = int64_t((kScratchBytes - kScrOrder) / 5);
+static_assert(kNoAllocMaxTiles == 3327488, "the limit stated in snerg.h");
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per device).
+int scratch_on_current_device(uint8_t** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SNERG_ERR_UNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(SNERG_ERR_HIP, "hipGetSymbolAddress returned NULL for the scratch array");
+        g_scratch_ptr[dev] = static_cast<uint8_t*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return SNERG_OK;
+}
+
+// Camera rows go to the device as kernel arguments (no staging buffer).
+constexpr int kCamsPerLaunch = 24;
+struct CamBatch {
+    DevCamera c[kCamsPerLaunch];
+    int32_t n, first;
+};
+static_assert(sizeof(CamBatch) + sizeof(void*) < 4096, "kernel arguments stay below 4 KB");
+
+__global__ void k_put_cams(CamBatch b, DevCamera* dst) {
+    const int i = int(threadIdx.x);
+    if (i < b.n) dst[b.first + i] = b.c[i];
+}
+
 }  // namespace
 
 extern "C" {
@@ -394,6 +446,14 @@ int snerg_create(snerg_handle** out) {
     if (e != hipSuccess) {
         snerg_destroy(h);
         return fail(SNERG_ERR_HIP, std::string("snerg_create: ") + hipGetErrorString(e));
+    }
+    // look up this device's scratch array now, so that snerg_render_noalloc
+    // finds it ready
+    uint8_t* scr = nullptr;
+    const int rc = scratch_on_current_device(&scr);
+    if (rc) {
+        snerg_destroy(h);
+        return rc;
     }
     *out = h;
     return SNERG_OK;
@@ -456,6 +516,100 @@ int snerg_render(snerg_handle* h, const snerg_grid* grid, const float* mlp, cons
     if (n_rays == 0) return SNERG_OK;
     return render_impl(h, grid, mlp, cams, n_cams, ray_ids, n_rays, opts, out_rgba, aux,
                        static_cast<hipStream_t>(stream), h->tuning);
+}
+
+int snerg_render_noalloc(snerg_handle* h, const snerg_grid* grid, const float* mlp, const snerg_camera* cams,
+                         int32_t n_cams, const int64_t* ray_ids, int64_t n_rays, const snerg_opts* opts,
+                         float* out_rgba, float* aux, void* stream) {
+    int64_t total = 0;
+    if (n_rays < 0) return fail(SNERG_ERR_INVALID_ARG, "n_rays must be >= 0");
+    int rc = common_render_checks(grid, mlp, true, cams, n_cams, ray_ids, n_rays, opts, &total);
+    if (rc) return rc;
+    if (!out_rgba) return fail(SNERG_ERR_INVALID_ARG, "out_rgba is NULL");
+    if (aux && (opts->flags & SNERG_FLAG_PER_SAMPLE_MLP))
+        return fail(SNERG_ERR_UNSUPPORTED, "aux is not produced with SNERG_FLAG_PER_SAMPLE_MLP");
+    if (opts->flags & SNERG_FLAG_GRAPH)
+        return fail(SNERG_ERR_UNSUPPORTED, "snerg_render_noalloc does not build graphs (instantiation allocates)");
+    if (!h) return fail(SNERG_ERR_INVALID_ARG, "handle is NULL");
+    if (n_cams > kNoAllocMaxCams)
+        return fail(SNERG_ERR_WORKSPACE, "snerg_render_noalloc takes at most 1024 cameras");
+    const snerg_tuning tu = h->tuning;
+    int64_t tiles = 0;
+    for (int32_t c = 0; c < n_cams; ++c)
+        tiles += int64_t((cams[c].W + tu.tile_w - 1) / tu.tile_w) * ((cams[c].H + tu.tile_h - 1) / tu.tile_h);
+    if (!ray_ids && tiles > kNoAllocMaxTiles)
+        return fail(SNERG_ERR_WORKSPACE, "snerg_render_noalloc takes at most " + std::to_string(kNoAllocMaxTiles) +
+                                             " tiles of 64 pixels per call");
+    uint8_t* base = nullptr;
+    if ((rc = scratch_on_current_device(&base))) return rc;
+    if (n_rays == 0) return SNERG_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DevCamera* d_cams = reinterpret_cast<DevCamera*>(base + kScrCams);
+    int32_t* counts = reinterpret_cast<int32_t*>(base + kScrCounts);
+    int32_t* counter = reinterpret_cast<int32_t*>(base + kScrCounter);
+    int32_t* order = reinterpret_cast<int32_t*>(base + kScrOrder);
+    uint8_t* cls = base + kScrOrder + size_t(4) * size_t(tiles);
+    // camera table, as in upload_cams
+    CamBatch b;
+    int64_t rays = 0, toff = 0;
+    for (int32_t c0 = 0; c0 < n_cams; c0 += kCamsPerLaunch) {
+        std::memset(&b, 0, sizeof b);
+        b.first = c0;
+        b.n = std::min<int32_t>(kCamsPerLaunch, n_cams - c0);
+        for (int32_t j = 0; j < b.n; ++j) {
+            const snerg_camera& k = cams[c0 + j];
+            DevCamera& d = b.c[j];
+            for (int a = 0; a < 3; ++a) {
+                d.eye[a] = k.eye[a];
+                d.fwd[a] = k.fwd[a];
+                d.right[a] = k.right[a];
+                d.up[a] = k.up[a];
+            }
+            d.focal = k.focal;
+            d.W = k.W;
+            d.H = k.H;
+            d.ray_offset = rays;
+            d.tile_offset = toff;
+            d.tiles_x = (k.W + tu.tile_w - 1) / tu.tile_w;
+            d.tiles_y = (k.H + tu.tile_h - 1) / tu.tile_h;
+            rays += int64_t(k.W) * k.H;
+            toff += int64_t(d.tiles_x) * d.tiles_y;
+        }
+        hipLaunchKernelGGL(k_put_cams, dim3(1), dim3(kCamsPerLaunch), 0, s, b, d_cams);
+        HIP_TRY(hipGetLastError());
+    }
+    RenderArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.grid = grid_args(grid);
+    a.opts = render_opts(opts);
+    a.mlp = mlp;
+    a.cams = d_cams;
+    a.n_cams = n_cams;
+    a.ray_ids = ray_ids;
+    a.n_rays = n_rays;
+    a.total_tiles = tiles;
+    a.tile_w = tu.tile_w;
+    a.tile_h = tu.tile_h;
+    a.tile_counter = counter;
+    a.out = out_rgba;
+    a.aux = aux;
+    const int vt = grid->dtype == SNERG_F32 ? 1 : 0;
+    const int mlp_mode = !opts->mlp_on ? kMlpOff : ((opts->flags & SNERG_FLAG_MLP_FP16) ? kMlpF16 : kMlpF32);
+    if (ray_ids) {
+        a.mode = kModeList;
+        HIP_TRY(launch_render(a, vt, mlp_mode, tu.waves_per_group, 0, s));
+        return SNERG_OK;
+    }
+    const bool persistent = (opts->flags & SNERG_FLAG_PERSISTENT) != 0;
+    a.mode = persistent ? kModePersistent : kModeTiles;
+    a.tile_order = order;
+    // the order kernels expect zero counters; the array keeps whatever the
+    // last call left, so clear them (a fill kernel, no memset node)
+    HIP_TRY(launch_fill_i32(counts, 64, 0, s));
+    HIP_TRY(launch_tile_order(a, cls, counts, order, s));
+    if (persistent) HIP_TRY(launch_fill_i32(counter, 1, 0, s));
+    HIP_TRY(launch_render(a, vt, mlp_mode, tu.waves_per_group, persistent ? h->n_cu * tu.groups_per_cu : 0, s));
+    return SNERG_OK;
 }
 
 int snerg_render_counted(snerg_handle* h, const snerg_grid* grid, const float* mlp, const snerg_camera* cams,

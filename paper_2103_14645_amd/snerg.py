@@ -106,6 +106,7 @@ def lib():
             "snerg_render": [_P, _P, _P, _P, i32, _P, i64, _P, _P, _P, _P],
             "snerg_render_backward": [_P, _P, _P, _P, i32, _P, i64, _P, _P, _P, _P, _P, _P, _P, _P],
             "snerg_render_counted": [_P, _P, _P, _P, i32, _P, i64, _P, _P, _P, _P, _P],
+            "snerg_render_noalloc": [_P, _P, _P, _P, i32, _P, i64, _P, _P, _P, _P],
             "snerg_trace_visits": [_P, _P, _P, i32, _P, i64, _P, i32, _P, _P, _P, _P],
             "snerg_set_tuning": [_P, _P],
             "snerg_get_tuning": [_P, _P],
@@ -130,7 +131,8 @@ def lib():
 
 
 EXPORTED = ["snerg_create", "snerg_destroy", "snerg_status_string", "snerg_last_error", "snerg_packed_size",
-            "snerg_pack_grid", "snerg_render", "snerg_render_backward", "snerg_render_counted", "snerg_trace_visits",
+            "snerg_pack_grid", "snerg_render", "snerg_render_backward", "snerg_render_counted", "snerg_render_noalloc",
+            "snerg_trace_visits",
             "snerg_set_tuning", "snerg_get_tuning", "snerg_autotune", "snerg_loss_mse", "snerg_adam_step",
             "snerg_bake_cull", "snerg_bake_quantize", "snerg_timing_enable", "snerg_timing_read"]
 
@@ -217,6 +219,13 @@ def snerg_render(handle, grid: snerg_grid, mlp, cams, ray_ids, n_rays, opts, out
     _check(lib().snerg_render(handle.h, ctypes.byref(grid), _ptr(mlp), cams, len(cams), _ptr(ray_ids),
                               int(n_rays), ctypes.byref(opts), _ptr(out_rgba), _ptr(aux), _stream(stream)),
            "snerg_render")
+
+
+def snerg_render_noalloc(handle, grid: snerg_grid, mlp, cams, ray_ids, n_rays, opts, out_rgba, aux=None,
+                         stream=None):
+    _check(lib().snerg_render_noalloc(handle.h, ctypes.byref(grid), _ptr(mlp), cams, len(cams), _ptr(ray_ids),
+                                      int(n_rays), ctypes.byref(opts), _ptr(out_rgba), _ptr(aux), _stream(stream)),
+           "snerg_render_noalloc")
 
 
 def snerg_render_counted(handle, grid: snerg_grid, mlp, cams, ray_ids, n_rays, opts, out_rgba, aux, counters,
