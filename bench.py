@@ -2,7 +2,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs plain,batched,adjoint,large,finetune,nondeferred,bake]
     python bench.py --legs plain,copy --no-cpu-baseline   # adds the copy-kernel calibration launches
-    python bench.py --source-hash                          # hash of the render kernel sources
+    python bench.py --source-hash                          # hash of the kernel sources
 
 Headline (value): forward Mrays/s of the plain FP32 path on the 512^3 grid
 (B = 32, ~10.6% occupied procedural shell) for one 800x800 camera, with
@@ -21,13 +21,17 @@ and baking a dense 512^3 field (both culls from 100 training views at
 Prints one JSON line on stdout; progress goes to stderr.
 
 ms_per_step is the whole snerg_render call (the tile-order pre-pass and the
-render kernel); roofline.achieved divides the algorithmic bytes by the
-render kernel's own duration, from HIP events the library records around
-that launch during the timed frames (snerg_timing_enable/read).
-roofline.traffic is the measured HBM traffic of one render launch, read from
-the committed counter summary for this kernel and workload; it is reported
-only while the hash of the render kernel sources equals the one recorded
-there (the counters describe that code), else null.
+render kernel).  The render kernel is bound by vector-ALU instruction issue
+(the committed counters: VALUs about 70% busy, HBM traffic about a tenth of
+peak), so roofline is the ALU roofline: the algorithmic FP32 work of the
+frame (per composited sample and per ray, from the march's exact counters)
+over the render kernel's own duration, from HIP events the library records
+around that launch during the timed frames (snerg_timing_enable/read),
+against the FP32 vector peak.  roofline.hbm gives the algorithmic bytes of
+the paper's accounting as an effective rate, and the measured HBM traffic
+(FETCH_SIZE + WRITE_SIZE of one launch, from profiles/counters_by_kernel.md)
+as a rate; both counter-derived figures are reported only while the hash of
+the kernel sources equals the one recorded there, else null.
 """
 from __future__ import annotations
 
@@ -46,37 +50,63 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP16_PEAK_TFLOPS = 2500.0  # dense FP16 MFMA
+# FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP (fused multiply-add) x 2 (packed FP32)
+# x 2.4 GHz = 157.3 TFLOP/s; this build emits no packed FP32 instructions, so 78.6 TFLOP/s is
+# the most its code can issue
+FP32_PEAK_TFLOPS = 157.3
+FP32_PEAK_UNPACKED_TFLOPS = 78.6
 MLP_FLOP = 2 * (34 * 16 + 16 * 16 + 16 * 3)
-RENDER_SOURCES = ("render.hip", "march.h", "mlp.h", "snerg_dev.h", "snerg_launch.h", "api.cpp")  # kernel and its launch order
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_render_plain512_traffic.md")
+# algorithmic FP32 work of the forward (Eq. 2, 5-7, Section 5.2): per composited sample 15 FLOP
+# of trilinear weights, 8 channels x 8 corners multiply-adds (128) and 20 of compositing; per
+# ray whose network runs, the network (1,696), 36 for the direction encoding, 9 for the sigmoid
+# and 7 for the output
+SAMPLE_FLOP = 15 + 128 + 20
+RAY_FLOP = MLP_FLOP + 36 + 9 + 7
+KERNEL_SOURCES = ("render.hip", "render_ps.hip", "backward.hip", "march.h", "mlp.h", "snerg_dev.h",
+                  "snerg_launch.h", "api.cpp")  # the kernels and their launch order
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "counters_by_kernel.md")
 COPY_BYTES = 1 << 30
 TIMING_EVERY = 4  # frames per kernel-timed frame in the plain leg's timed region
 
 
-def render_source_hash():
+def kernel_source_hash():
     h = hashlib.sha256()
-    for name in RENDER_SOURCES:
+    for name in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2103_14645_amd", "csrc", name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
 
 
-def measured_traffic():
-    """(bytes per launch, copy GB/s) from the committed counter summary if it
-    describes the current kernel sources ("key = value" lines), else
-    (None, None).  The copy rate is the plain 1 GiB copy measured in the
-    same counter run: what this HBM delivers to a streaming kernel."""
+def file_sha256(path):
+    h = hashlib.sha256()
+    with open(path, "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()
+
+
+def committed_counters():
+    """"key = value" figures of the committed counter summary (measured HBM
+    traffic per launch, instruction and busy fractions) if it describes the
+    current kernel sources, else {}: counters taken on other code say
+    nothing about this code."""
     try:
         kv = {}
-        for line in open(TRAFFIC_SUMMARY):
-            if "=" in line and not line.startswith(" "):
-                k, v = line.split("=", 1)
+        for line in open(COUNTER_SUMMARY):
+            if " = " in line and not line.startswith((" ", "|", "#")):
+                k, v = line.split(" = ", 1)
                 kv[k.strip().strip("`")] = v.strip().strip("`")
-        if kv.get("render_source_sha256") != render_source_hash():
-            return None, None
-        return int(kv["traffic_bytes_per_launch"]), float(kv["copy_read_write_gbs"])
-    except (OSError, KeyError, ValueError):
-        return None, None
+        if kv.get("kernel_source_sha256") != kernel_source_hash():
+            return {}
+        return kv
+    except OSError:
+        return {}
+
+
+def counter(kv, key, cast=float):
+    try:
+        return cast(kv[key])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(msg):
@@ -112,6 +142,22 @@ def launch_spread(fn, n, torch):
 
 
 def host_cpu():
+    """CPU model as lscpu reports it (with family/model/stepping, which name
+    the part when the model string is generic), else /proc/cpuinfo's."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        kv = {}
+        for line in out.splitlines():
+            if ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        if kv.get("Model name"):
+            return (f"{kv['Model name']} (family {kv.get('CPU family', '?')}, model {kv.get('Model', '?')}, "
+                    f"stepping {kv.get('Stepping', '?')}; {kv.get('Socket(s)', '?')} socket(s), "
+                    f"{kv.get('Thread(s) per core', '?')} thread(s) per core)")
+    except (OSError, subprocess.SubprocessError):
+        pass
     try:
         for line in open("/proc/cpuinfo"):
             if line.startswith("model name"):
@@ -135,14 +181,21 @@ def frame_counters(S, h, dg, cams):
     torch.cuda.synchronize()
     c = ctr.cpu().numpy().astype(np.int64)
     return dict(blocks=int(c[:, 0].sum()), occupied=int(c[:, 1].sum()), inblock=int(c[:, 2].sum()),
-                active=int(c[:, 3].sum()), rays=int(c.shape[0]))
+                active=int(c[:, 3].sum()), rays=int(c.shape[0]), gated=int((c[:, 3] > 0).sum()))
 
 
-def algorithmic_bytes(cnt):
+def algorithmic_bytes(cnt, value_bytes=8, out_bytes=16):
     """The method's own traffic per the paper's accounting (Appendix A): one
     indirection entry per macroblock traversed (4 B), one density byte per
-    in-block sample, 8 corners x 8 B per composited sample, 16 B of RGBA."""
-    return 4 * cnt["blocks"] + cnt["inblock"] + 64 * cnt["active"] + 16 * cnt["rays"]
+    in-block sample, 8 corners x value_bytes per composited sample (8 B for
+    the uint8 atlas, 32 B for the float32 shadow), out_bytes per ray."""
+    return 4 * cnt["blocks"] + cnt["inblock"] + 8 * value_bytes * cnt["active"] + out_bytes * cnt["rays"]
+
+
+def algorithmic_flop(cnt, network=True):
+    """Algorithmic FP32 work of the forward: SAMPLE_FLOP per composited
+    sample, RAY_FLOP per ray whose deferred network runs."""
+    return SAMPLE_FLOP * cnt["active"] + (RAY_FLOP * cnt["gated"] if network else 0)
 
 
 def tune_launch(S, h, grid, m, carr, out, reps, tiles=None, persistent=None):
@@ -150,14 +203,16 @@ def tune_launch(S, h, grid, m, carr, out, reps, tiles=None, persistent=None):
     issued by the hardware, or persistent workgroups pulling tiles from a
     counter) and keeps the faster: (opts, tuning, ms, mode)."""
     best = None
+    modes = {}
     for mode, cands in (("tiles", tiles), ("persistent", persistent)):
         opts = S.make_opts(fp16=True, persistent=(mode == "persistent"), graph=True)
         t, ms = S.snerg_autotune(h, grid, m, carr, opts, out, reps=reps, candidates=cands)
         log(f"  {mode}: {t} at {ms:.3f} ms")
+        modes[mode] = dict(tuning=list(t), ms=round(ms, 4))
         if best is None or ms < best[2]:
             best = (opts, t, ms, mode)
     S.snerg_set_tuning(h, *best[1])
-    return best
+    return best + (modes,)
 
 
 def leg_plain(args, torch, S, W, O):
@@ -208,7 +263,7 @@ def leg_batched(args, torch, S, W, O):
     carr = S.make_cameras(cams)
     log(f"batched1024: {g.n_blocks} blocks, {len(cams)} cameras, {n} rays; autotuning")
     grid = dg.struct()
-    opts, best, best_ms, mode = tune_launch(S, h, grid, m, carr, out, 2)
+    opts, best, best_ms, mode, modes = tune_launch(S, h, grid, m, carr, out, 2)
     log(f"batched1024: {mode} launch, tuning {best} at {best_ms:.3f} ms")
 
     def step():
@@ -223,20 +278,28 @@ def leg_batched(args, torch, S, W, O):
     # the deferred network: 1,696 FLOP per ray (34x16 + 16x16 + 16x3 multiply-adds); on MFMA tiles
     # 20 v_mfma_f32_16x16x16_f16 of 8,192 FLOP per 64 rays (K and N padded) are executed
     mlp_tflops = n * MLP_FLOP / (ms * 1e-3) / 1e12
+    cnt = frame_counters(S, h, dg, cams)
     res = dict(ms=ms, rays=n, mrays=n / ms / 1e3, max_abs_err=err, err_sample=len(ids), tuning=list(best),
-               mode=mode, cpu_mrays=cpu_mrays, mlp_tflops=mlp_tflops, mfma_frac=mlp_tflops / FP16_PEAK_TFLOPS,
-               mfma_tflops_executed=n / 64 * 20 * 8192 / (ms * 1e-3) / 1e12)
+               mode=mode, modes=modes, cpu_mrays=cpu_mrays, mlp_tflops=mlp_tflops,
+               mfma_frac=mlp_tflops / FP16_PEAK_TFLOPS,
+               mfma_tflops_executed=n / 64 * 20 * 8192 / (ms * 1e-3) / 1e12, counters=cnt,
+               alg_bytes=algorithmic_bytes(cnt), alg_flop=algorithmic_flop(cnt, network=False))
     log(f"batched1024: {ms:.3f} ms/batch, {res['mrays']:.1f} Mrays/s, fp16 max-abs err {err:.2e}; MLP "
         f"{mlp_tflops:.2f} TFLOP/s = {100 * res['mfma_frac']:.3f}% of the FP16 MFMA peak")
     return res
 
 
 def leg_adjoint(args, torch, S, W, O):
+    """One fine-tuning step of Eq. 3 on the float32 shadow of the 512^3 grid
+    over 8 views at 800x800: forward with the per-ray state, squared error
+    against targets rendered from a seeded perturbation (features scaled by
+    1 + 0.05 U[-1, 1] and clamped to [0, 1], every weight moved by
+    0.05 std(W) N(0, 1)), its gradient, and the backward to the 883 MLP
+    parameters and every grid value."""
     from paper_2103_14645_amd import autograd as A
     cfg = W.config("adjoint512")
     g, cams, mlp = cfg["grid"], cfg["cams"], cfg["mlp"]
     h = S.Handle()
-    r = A.ShadowRenderer(h, g.N, g.B, g.indirection, g.n_blocks)
     dens = torch.from_numpy(g.dens).cuda().float().div_(255.0)
     rgb = torch.from_numpy(g.rgb).cuda().float().div_(255.0)
     feat = torch.from_numpy(g.feat).cuda().float().div_(255.0)
@@ -244,41 +307,64 @@ def leg_adjoint(args, torch, S, W, O):
     carr = S.make_cameras(cams)
     n = sum(c.n_rays for c in cams)
     opts = S.make_opts()
+    # targets: the perturbed grid and network rendered once
+    pmlp, pfeat = W.perturbed(mlp, g)
+    rt = A.ShadowRenderer(h, g.N, g.B, g.indirection, g.n_blocks)
+    rt.pack(dens, rgb, torch.from_numpy(pfeat).cuda())
+    target = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    S.snerg_render(h, rt.struct(), S.mlp_tensor(pmlp), carr, None, n, opts, target)
+    del rt
+    r = A.ShadowRenderer(h, g.N, g.B, g.indirection, g.n_blocks)
     r.pack(dens, rgb, feat)
     grid = r.struct()
     out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
     aux = torch.empty((n, 8), dtype=torch.float32, device="cuda")
-    S.snerg_render(h, grid, m, carr, None, n, opts, out, aux)
-    gout = torch.randn((n, 4), device="cuda") / n
+    gout = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
     gm = torch.empty(883, device="cuda")
     gd, gr, gf = torch.empty_like(dens), torch.empty_like(rgb), torch.empty_like(feat)
 
     def fwd():
         S.snerg_render(h, grid, m, carr, None, n, opts, out, aux)
 
+    def mse():
+        S.snerg_loss_mse(h, out, target, n, gout, loss)
+
     def bwd():
         S.snerg_render_backward(h, grid, m, carr, None, n, opts, aux, gout, gm, gd, gr, gf)
 
-    log(f"adjoint512: {n} rays over {len(cams)} views")
+    def step():
+        fwd()
+        mse()
+        bwd()
+
+    log(f"adjoint512: {n} rays over {len(cams)} views, MSE against perturbed targets")
     steps = max(2, args.steps // 4)
     ms_f = time_launches(fwd, steps, 1, torch)
+    mse()
+    ms_l = time_launches(mse, steps, 1, torch)
     ms_b = time_launches(bwd, steps, 1, torch)
-    # Algorithmic bytes on the float32 shadow (same traversal as the uint8 grid: the zero
-    # pattern is the same).  Forward: 4 B per macroblock, 1 B per in-block sample, 8 corners x
-    # 32 B per composited sample, 16 B RGBA + 32 B aux per ray.  Backward: the re-march reads
-    # the same, plus aux, dL/dRGBA and the per-ray dL/d(C, V) (32 + 16 + 32 B per ray); the
-    # gradient scatter is not counted, so this is a lower bound.
+    ms_step = time_launches(step, steps, 1, torch)
+    loss_value = float(loss.item())
+    # Algorithmic bytes on the float32 shadow (its zero pattern is the uint8 grid's, so the
+    # traversal counters are the same): forward = 4 B per macroblock, 1 B per in-block sample,
+    # 8 corners x 32 B per composited sample, 16 B RGBA + 32 B aux per ray.  Backward = the same
+    # re-march reads, the gradient scatter's read-modify-write of 8 corners x 8 channels x 4 B per
+    # composited sample, and 12 B of dL/dRGB + 32 B of aux read per ray.
     dgu = S.DeviceGrid(h, g.N, g.B, g.indirection, g.dens, g.rgb, g.feat)
     cnt = frame_counters(S, h, dgu, cams)
     del dgu
     march = 4 * cnt["blocks"] + cnt["inblock"] + 256 * cnt["active"]
     fwd_bytes = march + 48 * cnt["rays"]
-    bwd_bytes = march + 80 * cnt["rays"]
-    res = dict(ms_fwd=ms_f, ms_bwd=ms_b, rays=n, fwd_mrays=n / ms_f / 1e3, bwd_mrays=n / ms_b / 1e3,
+    bwd_bytes = march + 256 * cnt["active"] + 44 * cnt["rays"]
+    res = dict(ms_fwd=ms_f, ms_bwd=ms_b, ms_loss=ms_l, ms_step=ms_step, rays=n, fwd_mrays=n / ms_f / 1e3,
+               bwd_mrays=n / ms_b / 1e3, step_mrays=n / ms_step / 1e3, loss=loss_value,
+               fwd_bytes=fwd_bytes, bwd_bytes=bwd_bytes,
                fwd_alg_gbs=fwd_bytes / (ms_f * 1e-3) / 1e9, bwd_alg_gbs=bwd_bytes / (ms_b * 1e-3) / 1e9,
                counters=cnt)
-    log(f"adjoint512: fwd {ms_f:.3f} ms, bwd {ms_b:.3f} ms -> {res['bwd_mrays']:.1f} bwd Mrays/s; algorithmic "
-        f"{res['fwd_alg_gbs']:.0f} / {res['bwd_alg_gbs']:.0f} GB/s (fwd / bwd, bwd a lower bound)")
+    log(f"adjoint512: fwd {ms_f:.3f} ms, loss {ms_l:.3f} ms, bwd {ms_b:.3f} ms -> {res['bwd_mrays']:.1f} bwd Mrays/s; "
+        f"step {ms_step:.3f} ms; loss {loss_value:.6f}; algorithmic {res['fwd_alg_gbs']:.0f} / "
+        f"{res['bwd_alg_gbs']:.0f} GB/s (fwd / bwd)")
     return res
 
 
@@ -299,7 +385,7 @@ def leg_large(args, torch, S, W, O):
     carr = S.make_cameras(cams)
     log(f"large1024: {g.n_blocks} blocks ({g.meta['occupancy']:.3f}), {len(cams)} cameras, {n} rays")
     grid = dg.struct()
-    opts, best, _, mode = tune_launch(S, h, grid, m, carr, out, 1,
+    opts, best, _, mode, modes = tune_launch(S, h, grid, m, carr, out, 1,
                                       tiles=[(8, 8, 4, 8), (8, 8, 2, 8), (16, 4, 4, 8)],
                                       persistent=[(8, 8, 4, 3), (8, 8, 4, 4), (8, 8, 2, 6), (8, 8, 4, 2)])
 
@@ -307,6 +393,7 @@ def leg_large(args, torch, S, W, O):
         S.snerg_render(h, grid, m, carr, None, n, opts, out)
 
     ms = time_launches(step, 2, 1, torch)
+    cnt = frame_counters(S, h, dg, cams)
     ids = torch.from_numpy(np.sort(np.random.default_rng(3).choice(n, 4096, replace=False))).cuda()
     frame = out[ids].cpu().numpy()
     ref, cpu_mrays = oracle_rate(O, O.OracleGrid(g), mlp, cams, ids.cpu().numpy(), args.cpu_threads)
@@ -359,7 +446,9 @@ def leg_large(args, torch, S, W, O):
     it[0] = 0
     ms_step_p = time_launches(train_step, 8, 2, torch)
     ms_f_p = time_launches(fwd_only, 8, 2, torch)
-    res = dict(ms=ms, rays=n, mrays=n / ms / 1e3, max_abs_err=err, tuning=list(best), mode=mode, mb=mb, cpu_mrays=cpu_mrays,
+    res = dict(ms=ms, rays=n, mrays=n / ms / 1e3, max_abs_err=err, tuning=list(best), mode=mode, modes=modes,
+               counters=cnt, alg_bytes=algorithmic_bytes(cnt), alg_flop=algorithmic_flop(cnt, network=False),
+               mb=mb, cpu_mrays=cpu_mrays,
                ms_train_step=ms_step, ms_mb_fwd=ms_f, bwd_mrays=mb / ms_b / 1e3,
                ms_train_step_patches=ms_step_p, ms_mb_fwd_patches=ms_f_p,
                bwd_mrays_patches=mb / max(ms_step_p - ms_f_p, 1e-6) / 1e3)
@@ -555,7 +644,7 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
     args = ap.parse_args()
     if args.source_hash:
-        print(render_source_hash())
+        print(kernel_source_hash())
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the render shards by rays "
@@ -588,8 +677,33 @@ def main():
 
     ms = plain["ms"]
     kms = plain["kernel_ms"]
-    achieved = plain["alg_bytes"] / (kms * 1e-3) / 1e9
-    traffic, copy_gbs = measured_traffic()
+    kv = committed_counters()
+    copy_gbs = counter(kv, "copy_read_write_gbs")
+
+    def measured(leg, kernel_ms):
+        """HBM traffic of one launch from the committed counters (FETCH_SIZE +
+        WRITE_SIZE, scaled by the copy calibration) and its rate at the live
+        kernel time; None when the counters describe other code."""
+        t = counter(kv, f"traffic.{leg}", int)
+        if not t:
+            return dict(traffic=None)
+        gbs = t / (kernel_ms * 1e-3) / 1e9
+        return dict(traffic=t, traffic_gbs=round(gbs, 1), traffic_frac_of_peak=round(gbs / HBM_PEAK_GBS, 4),
+                    traffic_frac_of_copy_bw=round(gbs / copy_gbs, 4) if copy_gbs else None)
+
+    def hbm_view(alg_bytes, kernel_ms, leg):
+        gbs = alg_bytes / (kernel_ms * 1e-3) / 1e9
+        d = dict(alg_bytes_per_launch=alg_bytes, effective_gbs=round(gbs, 1),
+                 effective_frac_of_peak=round(gbs / HBM_PEAK_GBS, 4))
+        if gbs > HBM_PEAK_GBS:
+            d["above_peak"] = ("the algorithmic bytes exceed what HBM could deliver in this time: most of them "
+                               "are served by the L2 and the Infinity Cache; traffic is what left the L2")
+        d.update(measured(leg, kernel_ms))
+        return d
+
+    alg_flop = algorithmic_flop(plain["counters"])
+    alu_tflops = alg_flop / (kms * 1e-3) / 1e12
+    limiter = {k: counter(kv, f"plain512.{k}") for k in ("valu_busy", "ta_busy", "l2_hit", "valu_insts_per_wave")}
     line = {
         "metric": "Mrays/s and fps at 800x800 (fwd, batched FP16-MLP vs plain FP32); bwd Mrays/s",
         "value": round(plain["mrays"], 3),
@@ -607,14 +721,21 @@ def main():
                                "one 800x800 camera (39 deg), FP32 34-16-16-3 MLP",
                    "fps_800x800": round(1000.0 / ms, 2), "rays": plain["rays"],
                    "launch_ms_p10_p50_p90": plain["spread"]},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "traffic_gbs": round(traffic / (kms * 1e-3) / 1e9, 1) if traffic else None,
-                     "traffic_frac_of_copy_bw": round(traffic / (kms * 1e-3) / 1e9 / copy_gbs, 4) if traffic else None,
+        # The render kernel is bound by vector-ALU issue (VALU ~70% busy, texture address path ~30%,
+        # L2 hit rate ~88%, HBM traffic ~10% of peak, by the committed counters), so the roofline is
+        # the ALU one: algorithmic FP32 work over the kernel's live duration against the FP32 peak.
+        "roofline": {"bound": "alu", "achieved": round(alu_tflops, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(alu_tflops / FP32_PEAK_TFLOPS, 4),
+                     "traffic": counter(kv, "traffic.plain512", int),
                      "kernel": "k_render<u8, fp32-mlp>", "kernel_ms": round(kms, 4),
                      "kernel_ms_source": f"HIP events around the render kernel launch on every {TIMING_EVERY}th of the "
                                          f"{args.steps} timed frames ({plain['kernel_n']} launches)",
-                     "alg_bytes_per_launch": plain["alg_bytes"],
+                     "alg_flop_per_launch": alg_flop,
+                     "alg_flop_basis": f"{SAMPLE_FLOP} FLOP per composited sample, {RAY_FLOP} per ray whose "
+                                       f"network runs",
+                     "frac_of_unpacked_fp32_peak": round(alu_tflops / FP32_PEAK_UNPACKED_TFLOPS, 4),
+                     "limiter_counters": limiter if any(v is not None for v in limiter.values()) else None,
+                     "hbm": hbm_view(plain["alg_bytes"], kms, "plain512"),
                      "counters": plain["counters"]},
     }
     legs_out = {}
@@ -624,33 +745,53 @@ def main():
                                          "fps_800x800_equiv": round(b["mrays"] / 0.64, 2),
                                          "max_abs_err_vs_oracle": b["max_abs_err"], "err_sample": b["err_sample"],
                                          "rays": b["rays"], "tuning": b["tuning"], "launch": b["mode"],
+                                         "launch_modes": b["modes"],
                                          "cpu_oracle_mrays": round(b["cpu_mrays"], 4),
+                                         "roofline_hbm": hbm_view(b["alg_bytes"], b["ms"], "batched1024"),
+                                         "roofline_alu": {"achieved": round(b["alg_flop"] / (b["ms"] * 1e-3) / 1e12, 3),
+                                                          "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                                          "frac": round(b["alg_flop"] / (b["ms"] * 1e-3) / 1e12
+                                                                        / FP32_PEAK_TFLOPS, 4),
+                                                          "note": "march and compositing FP32 work; the network "
+                                                                  "runs on MFMA (roofline_mfma)"},
                                          "roofline_mfma": {"bound": "mfma", "achieved": round(b["mlp_tflops"], 3),
                                                            "peak": FP16_PEAK_TFLOPS, "unit": "TFLOP/s",
                                                            "frac": round(b["mfma_frac"], 6),
                                                            "executed_tflops": round(b["mfma_tflops_executed"], 3),
                                                            "note": "algorithmic MLP FLOPs over the whole launch, "
-                                                                   "which the march bounds"}}
+                                                                   "which the march bounds"},
+                                         "counters": b["counters"]}
     if "adjoint_512" in extra:
         a = extra["adjoint_512"]
         legs_out["adjoint_512"] = {"bwd_mrays": round(a["bwd_mrays"], 3), "fwd_mrays": round(a["fwd_mrays"], 3),
+                                   "step_mrays": round(a["step_mrays"], 3),
                                    "ms_bwd": round(a["ms_bwd"], 4), "ms_fwd": round(a["ms_fwd"], 4),
-                                   "rays": a["rays"],
-                                   "roofline_hbm": {"fwd_gbs": round(a["fwd_alg_gbs"], 1),
-                                                    "bwd_gbs_lower_bound": round(a["bwd_alg_gbs"], 1),
-                                                    "peak": HBM_PEAK_GBS,
-                                                    "fwd_frac": round(a["fwd_alg_gbs"] / HBM_PEAK_GBS, 4),
-                                                    "bwd_frac_lower_bound": round(a["bwd_alg_gbs"] / HBM_PEAK_GBS, 4)}}
+                                   "ms_loss": round(a["ms_loss"], 4), "ms_step": round(a["ms_step"], 4),
+                                   "loss": a["loss"], "rays": a["rays"],
+                                   "loss_def": "mean over rays and RGB of (rgb - target)^2, targets rendered from "
+                                               "features x (1 + 0.05 U[-1,1]) and weights + 0.05 std N(0,1)",
+                                   "roofline_hbm_fwd": hbm_view(a["fwd_bytes"], a["ms_fwd"], "adjoint512_fwd"),
+                                   "roofline_hbm_bwd": hbm_view(a["bwd_bytes"], a["ms_bwd"], "adjoint512_bwd"),
+                                   "bwd_atomics_per_launch": counter(kv, "adjoint512_bwd.atomics", int),
+                                   "bwd_valu_busy": counter(kv, "adjoint512_bwd.valu_busy"),
+                                   "counters": a["counters"]}
     if "large_1024" in extra:
         b = extra["large_1024"]
         legs_out["large_1024"] = {"mrays": round(b["mrays"], 3), "ms": round(b["ms"], 3),
                                   "fps_800x800_equiv": round(b["mrays"] / 0.64, 2),
                                   "max_abs_err_vs_oracle": b["max_abs_err"], "rays": b["rays"],
-                                  "tuning": b["tuning"], "launch": b["mode"], "minibatch": b["mb"],
+                                  "tuning": b["tuning"], "launch": b["mode"], "launch_modes": b["modes"],
+                                  "roofline_hbm": hbm_view(b["alg_bytes"], b["ms"], "large1024"),
+                                  "roofline_alu": {"achieved": round(b["alg_flop"] / (b["ms"] * 1e-3) / 1e12, 3),
+                                                   "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                                   "frac": round(b["alg_flop"] / (b["ms"] * 1e-3) / 1e12
+                                                                 / FP32_PEAK_TFLOPS, 4)},
+                                  "minibatch": b["mb"],
                                   "ms_minibatch_fwd_bwd": round(b["ms_train_step"], 4),
                                   "bwd_mrays": round(b["bwd_mrays"], 3), "cpu_oracle_mrays": round(b["cpu_mrays"], 4),
                                   "ms_minibatch_fwd_bwd_patches": round(b["ms_train_step_patches"], 4),
-                                  "bwd_mrays_patches": round(b["bwd_mrays_patches"], 3)}
+                                  "bwd_mrays_patches": round(b["bwd_mrays_patches"], 3),
+                                  "counters": b["counters"]}
     if "nondeferred" in extra:
         legs_out["nondeferred_512"] = {k: {kk: round(vv, 5) for kk, vv in v.items()}
                                        for k, v in extra["nondeferred"].items()}
@@ -662,6 +803,10 @@ def main():
         legs_out["bake_512"] = {k: (round(v, 5) if isinstance(v, float) else v) for k, v in extra["bake"].items()}
     if "copy" in extra:
         legs_out["copy_calibration"] = {k: round(v, 4) for k, v in extra["copy"].items()}
+    line["library"] = {"path": "paper_2103_14645_amd/libsnerg.so",
+                       "sha256": file_sha256(os.path.join(ROOT, "paper_2103_14645_amd", "libsnerg.so")),
+                       "kernel_source_sha256": kernel_source_hash(),
+                       "counter_summary_matches_sources": bool(kv)}
     line["legs"] = legs_out
     if not args.no_cpu_baseline:
         log("cpu baseline (FP64 oracle)")

@@ -29,13 +29,23 @@ def test_algorithmic_bytes_follow_the_per_unit_figures():
     assert b.algorithmic_bytes(cnt) == 4 * 10 + 100 + 64 * 7 + 16 * 3
 
 
-def test_traffic_figure_is_tied_to_the_render_sources():
+def test_algorithmic_flop_follow_the_per_unit_figures():
     b = _bench()
-    traffic, copy_gbs = b.measured_traffic()
+    cnt = {"active": 7, "gated": 3}
+    assert b.SAMPLE_FLOP == 15 + 128 + 20 and b.RAY_FLOP == 2 * (34 * 16 + 16 * 16 + 16 * 3) + 36 + 9 + 7
+    assert b.algorithmic_flop(cnt) == 7 * b.SAMPLE_FLOP + 3 * b.RAY_FLOP
+    assert b.algorithmic_flop(cnt, network=False) == 7 * b.SAMPLE_FLOP
+    # float32 shadow: 8 corners x 32 B per composited sample
+    cnt = {"blocks": 10, "inblock": 100, "active": 7, "rays": 3}
+    assert b.algorithmic_bytes(cnt, value_bytes=32, out_bytes=48) == 4 * 10 + 100 + 256 * 7 + 48 * 3
+
+
+def test_counter_figures_are_tied_to_the_kernel_sources():
+    b = _bench()
+    kv = b.committed_counters()
     # the committed counter summary either describes these sources or is ignored
-    if traffic is None:
-        assert copy_gbs is None
-    else:
-        assert traffic > 0 and copy_gbs > 0
-        with open(b.TRAFFIC_SUMMARY) as f:
-            assert b.render_source_hash() in f.read()
+    if kv:
+        assert kv["kernel_source_sha256"] == b.kernel_source_hash()
+        assert int(kv["traffic.plain512"]) > 0 and float(kv["copy_read_write_gbs"]) > 0
+    with open(b.COUNTER_SUMMARY) as f:
+        assert "kernel_source_sha256 = " in f.read()

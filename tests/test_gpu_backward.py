@@ -210,12 +210,31 @@ def test_large1024_fp16_minibatch_full_size():
     rng = np.random.default_rng(6)
     g_rgba = rng.normal(size=(len(ids), 4)) / len(ids)
     say(f"large1024 fp16 minibatch: {len(ids)} rays of {n}, {g.n_blocks} blocks")
-    gm, gd, gr, gf, _ = run_backward(g, vals, mlp, cams, g_rgba, ids=ids, fp16=True)
-    aux = O.render(og, mlp, cams, ray_ids=ids)["aux"]
+    gm, gd, gr, gf, out = run_backward(g, vals, mlp, cams, g_rgba, ids=ids, fp16=True)
+    orc = O.render(og, mlp, cams, ray_ids=ids)
     dirs = F.directions_of(cams, g.N, ids)
-    dW16, gcv16 = F.mlp_backward_fp16(mlp, aux, dirs, g_rgba)
+    dW16, gcv16 = F.mlp_backward_fp16(mlp, orc["aux"], dirs, g_rgba)
     _, ed, er, ef = O.render_grad(og, mlp, cams, g_rgba, ray_ids=ids, g_cv=gcv16)
     compare("mlp vs fp16 emulation", gm, dW16, rel=1e-3)
     compare("dens vs fp16 emulation", gd, ed, rel=1e-3)
     compare("rgb vs fp16 emulation", gr, er, rel=1e-3)
     compare("feat vs fp16 emulation", gf, ef, rel=1e-3)
+    # and against the exact FP64 gradient.  The bar is the one the FP16
+    # arithmetic itself sets: 5% of max|g| (half-precision operands three
+    # layers deep, about 2% on the 64^3 case), or 1.5 times the distance of
+    # the FP16 emulation from the exact gradient where that is larger (the
+    # feature gradient reaches the grid only through the network's input
+    # gradient, a sum over 16 hidden units whose terms cancel, so the FP16
+    # operand rounding is a larger share of it); and the forward at the FP16
+    # render bar
+    om, od, orr, of = O.render_grad(og, mlp, cams, g_rgba, ray_ids=ids)
+    _, ed16, er16, ef16 = O.render_grad(og, mlp, cams, g_rgba, ray_ids=ids, g_cv=gcv16)
+    for name, a_, b_, e_ in (("mlp", gm, om, dW16), ("dens", gd, od, ed16), ("rgb", gr, orr, er16),
+                             ("feat", gf, of, ef16)):
+        scale = float(np.abs(b_).max())
+        fp16_own = float(np.abs(e_ - b_).max())
+        err = float(np.abs(a_ - b_).max())
+        bar = max(5e-2 * scale, 1.5 * fp16_own) + 1e-7
+        say(f"  {name} vs exact: max|ref|={scale:.3e} max_err={err:.3e} fp16 emulation's own {fp16_own:.3e}")
+        assert err <= bar, name
+    assert np.abs(out - orc["rgba"]).max() <= 2e-3
