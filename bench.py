@@ -432,6 +432,12 @@ def leg_large(args, torch, S, W, O):
     ms_step = time_launches(train_step, 8, 2, torch)
     ms_f = time_launches(fwd_only, 8, 2, torch)
     ms_b = max(ms_step - ms_f, 1e-6)
+    # the same minibatches with gradient accumulation (SNERG_FLAG_ACCUMULATE): the
+    # backward adds into the arrays instead of clearing the 2.8 GB of grid gradients first
+    bo[0] = S.make_opts(fp16=True, accumulate=True)
+    gm.zero_(); gd.zero_(); gr.zero_(); gf.zero_()
+    ms_step_acc = time_launches(train_step, 8, 2, torch)
+    bo[0] = S.make_opts(fp16=True)
     # the same with minibatches of 1,024 whole 8x8 patches drawn across the 64 views
     tx, ty = cams[0].W // 8, cams[0].H // 8
     tiles = torch.randperm(len(cams) * tx * ty, device="cuda", generator=gen)[: 4 * (mb // 64)].view(4, -1)
@@ -450,10 +456,12 @@ def leg_large(args, torch, S, W, O):
                counters=cnt, alg_bytes=algorithmic_bytes(cnt), alg_flop=algorithmic_flop(cnt, network=False),
                mb=mb, cpu_mrays=cpu_mrays,
                ms_train_step=ms_step, ms_mb_fwd=ms_f, bwd_mrays=mb / ms_b / 1e3,
+               ms_train_step_accumulate=ms_step_acc, bwd_mrays_accumulate=mb / max(ms_step_acc - ms_f, 1e-6) / 1e3,
                ms_train_step_patches=ms_step_p, ms_mb_fwd_patches=ms_f_p,
                bwd_mrays_patches=mb / max(ms_step_p - ms_f_p, 1e-6) / 1e3)
     log(f"large1024: {ms:.1f} ms/launch, {res['mrays']:.1f} Mrays/s, fp16 err {err:.2e}; minibatch fwd+bwd "
-        f"{ms_step:.2f} ms (bwd {res['bwd_mrays']:.1f} Mrays/s); as 8x8 patches {ms_step_p:.2f} ms "
+        f"{ms_step:.2f} ms (bwd {res['bwd_mrays']:.1f} Mrays/s; accumulating {ms_step_acc:.2f} ms, bwd "
+        f"{res['bwd_mrays_accumulate']:.1f} Mrays/s); as 8x8 patches {ms_step_p:.2f} ms "
         f"(bwd {res['bwd_mrays_patches']:.1f} Mrays/s)")
     return res
 
@@ -789,6 +797,8 @@ def main():
                                   "minibatch": b["mb"],
                                   "ms_minibatch_fwd_bwd": round(b["ms_train_step"], 4),
                                   "bwd_mrays": round(b["bwd_mrays"], 3), "cpu_oracle_mrays": round(b["cpu_mrays"], 4),
+                                  "ms_minibatch_fwd_bwd_accumulate": round(b["ms_train_step_accumulate"], 4),
+                                  "bwd_mrays_accumulate": round(b["bwd_mrays_accumulate"], 3),
                                   "ms_minibatch_fwd_bwd_patches": round(b["ms_train_step_patches"], 4),
                                   "bwd_mrays_patches": round(b["bwd_mrays_patches"], 3),
                                   "counters": b["counters"]}

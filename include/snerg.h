@@ -115,6 +115,12 @@ extern "C" {
  * before the device atomics, as it does for whole views.  Results are the
  * same up to float summation order; with scattered rays it is slower. */
 #define SNERG_FLAG_PATCH_RAYS (1u << 7)
+/* Backward: add the gradients into grad_mlp, grad_dens, grad_rgb and
+ * grad_feat instead of overwriting them (gradient accumulation over
+ * minibatches; the caller zeroes the arrays when it starts a sum).  Skips
+ * the pass that clears the grid-gradient arrays, which for a small
+ * minibatch on a large grid costs more than the minibatch itself. */
+#define SNERG_FLAG_ACCUMULATE (1u << 8)
 
 #define SNERG_MLP_PARAMS 883 /* W1[16][34] b1[16] W2[16][16] b2[16] W3[3][16] b3[3], [out][in] */
 
@@ -211,8 +217,8 @@ int snerg_render(snerg_handle *h, const snerg_grid *grid, const float *mlp, cons
  * grid->dtype must be SNERG_F32.  Rays are re-marched (nothing per sample
  * is stored); aux must come from snerg_render of the same rays, grid, MLP,
  * cameras and options.  grad_rgba: device [n_rays][4].  Outputs (device,
- * overwritten, not accumulated): grad_mlp [883], grad_dens, grad_rgb,
- * grad_feat in canonical atlas layout.  Gradient sums use float32 atomics,
+ * overwritten, or added to with SNERG_FLAG_ACCUMULATE): grad_mlp [883],
+ * grad_dens, grad_rgb, grad_feat in canonical atlas layout.  Gradient sums use float32 atomics,
  * so their rounding depends on scheduling.  With SNERG_FLAG_MLP_FP16 the MLP
  * backward runs on FP16 MFMA tiles with FP32 accumulation (as the forward).
  * With SNERG_FLAG_MLP_GRAD_ONLY only grad_mlp is computed (the fine-tuning

@@ -93,7 +93,7 @@ int check_opts(const snerg_opts* o) {
     if (!std::isfinite(o->t_stop) || o->t_stop < 0.0f) return fail(SNERG_ERR_INVALID_ARG, "opts->t_stop must be finite and >= 0");
     const uint32_t known = SNERG_FLAG_MLP_FP16 | SNERG_FLAG_PERSISTENT | SNERG_FLAG_GRAPH | SNERG_FLAG_MLP_GRAD_ONLY |
                            SNERG_FLAG_NN_GATE | SNERG_FLAG_UNPREMULTIPLY | SNERG_FLAG_PER_SAMPLE_MLP |
-                           SNERG_FLAG_PATCH_RAYS;
+                           SNERG_FLAG_PATCH_RAYS | SNERG_FLAG_ACCUMULATE;
     if (o->flags & ~known) return fail(SNERG_ERR_UNSUPPORTED, "unknown opts->flags bits");
     return SNERG_OK;
 }
@@ -696,12 +696,13 @@ int snerg_render_backward(snerg_handle* h, const snerg_grid* grid, const float* 
     int64_t total_tiles = 0;
     rc = upload_cams(h, cams, n_cams, h->tuning.tile_w, h->tuning.tile_h, s, &total_tiles);
     if (rc) return rc;
-    if (!mlp_only) {
+    const bool accumulate = (opts->flags & SNERG_FLAG_ACCUMULATE) != 0;
+    if (!mlp_only && !accumulate) {
         HIP_TRY(launch_fill_f32(grad_dens, nv, 0.0f, s));
         HIP_TRY(launch_fill_f32(grad_rgb, nv * 3, 0.0f, s));
         HIP_TRY(launch_fill_f32(grad_feat, nv * 4, 0.0f, s));
     }
-    HIP_TRY(launch_fill_f32(grad_mlp, kMlpParams, 0.0f, s));
+    if (!accumulate) HIP_TRY(launch_fill_f32(grad_mlp, kMlpParams, 0.0f, s));
     if (n_rays == 0) return SNERG_OK;
     BackwardArgs a;
     std::memset(&a, 0, sizeof a);

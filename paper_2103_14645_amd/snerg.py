@@ -41,6 +41,7 @@ SNERG_FLAG_NN_GATE = 1 << 4
 SNERG_FLAG_UNPREMULTIPLY = 1 << 5
 SNERG_FLAG_PER_SAMPLE_MLP = 1 << 6
 SNERG_FLAG_PATCH_RAYS = 1 << 7
+SNERG_FLAG_ACCUMULATE = 1 << 8
 
 SNERG_MLP_PARAMS = 883
 
@@ -172,7 +173,7 @@ def make_cameras(cams):
 
 def make_opts(bg=(1.0, 1.0, 1.0), t_stop=1e-3, early_stop=True, mlp_on=True, fp16=False,
               persistent=False, graph=False, mlp_grad_only=False, nn_gate=False, unpremultiply=False,
-              per_sample_mlp=False, patch_rays=False):
+              per_sample_mlp=False, patch_rays=False, accumulate=False):
     o = snerg_opts()
     o.bg[:] = [float(v) for v in bg]
     o.t_stop = float(t_stop)
@@ -181,7 +182,8 @@ def make_opts(bg=(1.0, 1.0, 1.0), t_stop=1e-3, early_stop=True, mlp_on=True, fp1
     o.flags = ((SNERG_FLAG_MLP_FP16 if fp16 else 0) | (SNERG_FLAG_PERSISTENT if persistent else 0)
                | (SNERG_FLAG_GRAPH if graph else 0) | (SNERG_FLAG_MLP_GRAD_ONLY if mlp_grad_only else 0)
                | (SNERG_FLAG_NN_GATE if nn_gate else 0) | (SNERG_FLAG_UNPREMULTIPLY if unpremultiply else 0)
-               | (SNERG_FLAG_PER_SAMPLE_MLP if per_sample_mlp else 0) | (SNERG_FLAG_PATCH_RAYS if patch_rays else 0))
+               | (SNERG_FLAG_PER_SAMPLE_MLP if per_sample_mlp else 0) | (SNERG_FLAG_PATCH_RAYS if patch_rays else 0)
+               | (SNERG_FLAG_ACCUMULATE if accumulate else 0))
     return o
 
 

@@ -238,3 +238,51 @@ def test_large1024_fp16_minibatch_full_size():
         say(f"  {name} vs exact: max|ref|={scale:.3e} max_err={err:.3e} fp16 emulation's own {fp16_own:.3e}")
         assert err <= bar, name
     assert np.abs(out - orc["rgba"]).max() <= 2e-3
+
+
+@pytest.mark.parametrize("patch", [False, True])
+def test_accumulate_flag_adds_minibatch_gradients(patch):
+    # SNERG_FLAG_ACCUMULATE: two minibatches added into the same arrays give
+    # the sum of the two overwriting calls (up to float summation order), and
+    # the sum matches the oracle's gradient of both minibatches together
+    say(f"backward with SNERG_FLAG_ACCUMULATE, patch lists={patch}")
+    seed = 9
+    g = W.tiny_grid(n_occupied=160, seed=seed)
+    vals = shadow_values(g, seed)
+    mlp = W.mlp_weights(seed + 1)
+    cams = [W.orbit_camera(40, 32, seed=seed + 2)]
+    n = cams[0].n_rays
+    og = O.OracleGrid(g, values=vals)
+    ids = stable_ids(og, mlp, cams, np.random.default_rng(seed).permutation(n)[: (n // 128) * 128])
+    ids = ids[: (len(ids) // 128) * 128]
+    halves = (ids[: len(ids) // 2], ids[len(ids) // 2:])
+    rng = np.random.default_rng(seed + 5)
+    g_rgba = rng.normal(size=(len(ids), 4)) / len(ids)
+    h = handle()
+    r = A.ShadowRenderer(h, g.N, g.B, g.indirection, g.n_blocks)
+    dens, rgb, feat = (torch.from_numpy(v).cuda() for v in vals)
+    r.pack(dens, rgb, feat)
+    m = S.mlp_tensor(mlp)
+    carr = S.make_cameras(cams)
+    outs = {}
+    for acc in (False, True):
+        gm = torch.zeros(883, device="cuda")
+        gd, gr, gf = torch.zeros_like(dens), torch.zeros_like(rgb), torch.zeros_like(feat)
+        total = [np.zeros(883), np.zeros(vals[0].shape), np.zeros(vals[1].shape), np.zeros(vals[2].shape)]
+        for k, part in enumerate(halves):
+            idt = torch.from_numpy(part.astype(np.int64)).cuda()
+            gpart = torch.from_numpy(g_rgba[k * len(halves[0]):(k + 1) * len(halves[0])].astype(np.float32)).cuda()
+            opts = S.make_opts(accumulate=acc, patch_rays=patch)
+            out = torch.empty((len(part), 4), device="cuda")
+            aux = torch.empty((len(part), 8), device="cuda")
+            S.snerg_render(h, r.struct(), m, carr, idt, len(part), opts, out, aux)
+            S.snerg_render_backward(h, r.struct(), m, carr, idt, len(part), opts, aux, gpart, gm, gd, gr, gf)
+            torch.cuda.synchronize()
+            if not acc:
+                for t_, x in zip(total, (gm, gd, gr, gf)):
+                    t_ += x.cpu().numpy()
+        outs[acc] = total if not acc else [x.cpu().numpy().astype(np.float64) for x in (gm, gd, gr, gf)]
+    ref = O.render_grad(og, mlp, cams, g_rgba, ray_ids=ids)
+    for name, a_, b_, o_ in zip(("mlp", "dens", "rgb", "feat"), outs[True], outs[False], ref):
+        compare(name + " accumulated vs summed", a_, b_)
+        compare(name + " accumulated vs oracle", a_, o_)
