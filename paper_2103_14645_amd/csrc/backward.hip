@@ -72,9 +72,7 @@ __device__ __forceinline__ half4_t to_half4(float4_t v) {
 // so every D tile (after its element-wise step) is the next B operand.
 __device__ __forceinline__ void mlp_backward_f16_wave(const BackwardArgs& a, cfloat* W, const _Float16* xs,
                                                       const float* gsm, float* stage, int64_t base, int lane) {
-    half4_t w1[3];
-#pragma unroll
-    for (int kc = 0; kc < 3; ++kc) w1[kc] = a_frag(W + kOffW1, kMlpH, kMlpIn, 0, 16 * kc, lane);
+    const half8_t w1[2] = {a_frag32(W + kOffW1, kMlpIn, 0, lane), a_frag32(W + kOffW1, kMlpIn, 1, lane)};
     const half4_t w2 = a_frag(W + kOffW2, kMlpH, kMlpH, 0, 0, lane);
     const half4_t w3 = a_frag(W + kOffW3, kMlpOut, kMlpH, 0, 0, lane);
     const half4_t w3t = a_frag_t(W + kOffW3, kMlpOut, kMlpH, lane);
@@ -88,12 +86,9 @@ __device__ __forceinline__ void mlp_backward_f16_wave(const BackwardArgs& a, cfl
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         const int ray = 16 * g + n;  // this lane's column
-        const _Float16* row = xs + ray * kXRow + rq;
-        float4_t h1 = bb1;
-#pragma unroll
-        for (int kc = 0; kc < 3; ++kc)
-            h1 = __builtin_amdgcn_mfma_f32_16x16x16f16(w1[kc], *reinterpret_cast<const half4_t*>(row + 16 * kc), h1,
-                                                       0, 0, 0);
+        const _Float16 (*rows)[kXRow] = reinterpret_cast<const _Float16 (*)[kXRow]>(xs);
+        float4_t h1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(w1[0], x_frag32(rows, g, 0, lane), bb1, 0, 0, 0);
+        h1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(w1[1], x_frag32(rows, g, 1, lane), h1, 0, 0, 0);
 #pragma unroll
         for (int v = 0; v < 4; ++v) h1[v] = fmaxf(h1[v], 0.0f);
         float4_t h2 = __builtin_amdgcn_mfma_f32_16x16x16f16(w2, to_half4(h1), bb2, 0, 0, 0);

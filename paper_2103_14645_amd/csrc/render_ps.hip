@@ -65,6 +65,9 @@ __global__ __launch_bounds__(256) void k_render_ps(RenderArgs a) {
     const int wpg = blockDim.x >> 6;
     cfloat* W = as_const(a.mlp);
     const bool use_mlp = a.opts.mlp_on != 0;
+    // FP16 path: the weights as MFMA fragments, once per wavefront
+    MlpFragsF16 frags;
+    if (F16 && use_mlp) frags = mlp_frags_f16(W);
     const float cs = VT == 0 ? (1.0f / 255.0f) : 1.0f;
     const float kx = g.sigma_scale * cs / float(g.N);
     const float t_stop = a.opts.t_stop;
@@ -139,7 +142,7 @@ __global__ __launch_bounds__(256) void k_render_ps(RenderArgs a) {
                         for (int ch = 0; ch < 3; ++ch) xs[wave][lane][ch] = _Float16(pc[ch]);
 #pragma unroll
                         for (int ch = 0; ch < 4; ++ch) xs[wave][lane][3 + ch] = _Float16(pv[ch]);
-                        mlp_eval_f16_wave(W, xs[wave], pending, R);
+                        mlp_eval_f16_wave(frags, xs[wave], pending, R);
                     } else if (pending) {
                         const float xi[7] = {pc[0], pc[1], pc[2], pv[0], pv[1], pv[2], pv[3]};
                         float h2[kMlpH];
