@@ -167,10 +167,11 @@ typedef struct {
  * (camera table, tile counter, the render's tile-order scratch, the backward
  * pass's MLP partial sums and per-ray dL/dC_d, dL/dV scratch, the baking
  * scratch), a cached HIP graph, timing events and the tuning; nothing the
- * caller passes in.  The buffers are allocated on first use and grown when a
- * call needs more (the growing call waits for the device first), so a call
- * made inside a caller's stream capture must have been made once outside it
- * with the same sizes.  Calls on one handle should use one stream (or the
+ * caller passes in.  The buffers are allocated on first use and grown (by
+ * half again as much as the call needs) when a call needs more; the growing
+ * call first waits for the work queued on its stream, so a call made inside
+ * a caller's stream capture must have been made once outside it with the
+ * same sizes, and snerg_render_noalloc needs no buffer at all.  Calls on one handle should use one stream (or the
  * caller orders the streams). */
 int snerg_create(snerg_handle **out);
 int snerg_destroy(snerg_handle *h);
@@ -384,12 +385,34 @@ int snerg_get_tuning(snerg_handle *h, snerg_tuning *t);
  * SNERG_FLAG_PERSISTENT also 2, 3, 4, 6 or 8 resident workgroups per CU).
  * The launch mode itself (tiles or persistent) is the one opts selects.
  * out_rgba receives the last render.  best (host, nullable) receives the
- * winner and best_ms its time per render.  Synchronises `stream`.
+ * winner and best_ms its time per render.  The winner becomes the handle's
+ * tuning and is recorded for this workload (snerg_tuning_lookup).
+ * Synchronises `stream`.
  */
 int snerg_autotune(snerg_handle *h, const snerg_grid *grid, const float *mlp,
                    const snerg_camera *cams, int32_t n_cams, const snerg_opts *opts,
                    const snerg_tuning *candidates, int32_t n_candidates, int32_t reps,
                    float *out_rgba, snerg_tuning *best, float *best_ms, void *stream);
+
+/*
+ * Launch shapes by workload.  snerg_autotune also records its winner under
+ * the call's workload signature (a hash of the grid's N, B, block count and
+ * value type, every camera's image size, the kernel-selecting option flags,
+ * mlp_on and early_stop); snerg_render, snerg_render_counted and
+ * snerg_render_noalloc then use the recorded shape for a matching workload
+ * and the handle's tuning (snerg_set_tuning) otherwise.
+ * snerg_tuning_lookup writes the shape a render of this workload would use
+ * to *t and whether it was recorded (*found = 1) or is the handle's (0).
+ * snerg_tuning_save writes the recorded shapes to a text file (one line per
+ * workload: hexadecimal signature, tile_w, tile_h, waves_per_group,
+ * groups_per_cu) and snerg_tuning_load adds a file's entries to the handle
+ * (SNERG_ERR_INVALID_ARG, and nothing added, for an unreadable file, a
+ * malformed line or an invalid shape).  Host only.
+ */
+int snerg_tuning_lookup(snerg_handle *h, const snerg_grid *grid, const snerg_camera *cams, int32_t n_cams,
+                        const snerg_opts *opts, snerg_tuning *t, int32_t *found);
+int snerg_tuning_save(snerg_handle *h, const char *path);
+int snerg_tuning_load(snerg_handle *h, const char *path);
 
 /* ----------------------------------------------------------- measurement */
 

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "snerg.h"
@@ -168,6 +169,8 @@ struct snerg_handle {
     std::vector<hipEvent_t> t_start, t_stop;
     int64_t t_count = 0;
     snerg_tuning tuning = {8, 8, 4, 8};
+    // autotuned launch shapes by workload signature (tuning_signature)
+    std::unordered_map<uint64_t, snerg_tuning> tuned;
     // cached graph of {counter reset, persistent render}
     hipGraphExec_t graph_exec = nullptr;
     std::vector<uint8_t> graph_key;
@@ -225,15 +228,21 @@ int upload_cams(snerg_handle* h, const snerg_camera* cams, int32_t n_cams, int t
     return SNERG_OK;
 }
 
-// Grows a handle-owned float buffer (waits for queued work before freeing).
-int ensure_buffer(float** buf, size_t* cap, size_t need) {
+// Grows a handle-owned float buffer.  The old buffer may still be read by
+// work queued on the handle's stream, so that work is waited for before the
+// buffer is freed; growing by half again as much as asked keeps a sequence
+// of slowly growing calls from reallocating (and waiting) every time.
+int ensure_buffer(float** buf, size_t* cap, size_t need, hipStream_t s) {
     if (need <= *cap) return SNERG_OK;
-    HIP_TRY(hipDeviceSynchronize());
-    if (*buf) HIP_TRY(hipFree(*buf));
+    if (*buf) {
+        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(hipFree(*buf));
+    }
     *buf = nullptr;
     *cap = 0;
-    HIP_TRY(hipMalloc(buf, need * sizeof(float)));
-    *cap = need;
+    const size_t want = need + need / 2;
+    HIP_TRY(hipMalloc(buf, want * sizeof(float)));
+    *cap = want;
     return SNERG_OK;
 }
 
@@ -265,6 +274,36 @@ hipError_t timing_end(snerg_handle* h, hipStream_t s) {
     hipError_t e = hipEventRecord(h->t_stop[size_t(h->t_count % kTimingRing)], s);
     ++h->t_count;
     return e;
+}
+
+// What a launch shape's speed depends on: the grid's shape and occupancy,
+// the image sizes, and the options that select a kernel (FNV-1a over them).
+uint64_t tuning_signature(const snerg_grid* g, const snerg_camera* cams, int32_t n_cams, const snerg_opts* o) {
+    uint64_t x = 1469598103934665603ull;
+    auto mix = [&](int64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            x ^= uint64_t(v >> (8 * b)) & 0xFFu;
+            x *= 1099511628211ull;
+        }
+    };
+    mix(g->N); mix(g->B); mix(g->n_blocks); mix(g->dtype);
+    mix(n_cams);
+    for (int32_t c = 0; c < n_cams; ++c) { mix(cams[c].W); mix(cams[c].H); }
+    const uint32_t kernel_flags = SNERG_FLAG_MLP_FP16 | SNERG_FLAG_PERSISTENT | SNERG_FLAG_GRAPH | SNERG_FLAG_NN_GATE |
+                                  SNERG_FLAG_UNPREMULTIPLY | SNERG_FLAG_PER_SAMPLE_MLP;
+    mix(o->flags & kernel_flags); mix(o->mlp_on ? 1 : 0); mix(o->early_stop ? 1 : 0);
+    return x;
+}
+
+// The launch shape for a render: the autotuned one for this workload if
+// there is one, else the handle's.
+snerg_tuning tuning_for(const snerg_handle* h, const snerg_grid* g, const snerg_camera* cams, int32_t n_cams,
+                        const snerg_opts* o) {
+    if (!h->tuned.empty()) {
+        auto it = h->tuned.find(tuning_signature(g, cams, n_cams, o));
+        if (it != h->tuned.end()) return it->second;
+    }
+    return h->tuning;
 }
 
 int render_impl(snerg_handle* h, const snerg_grid* grid, const float* mlp, const snerg_camera* cams,
@@ -309,7 +348,7 @@ int render_impl(snerg_handle* h, const snerg_grid* grid, const float* mlp, const
     if (total_tiles <= int64_t(INT32_MAX)) {
         const size_t order_words = 64 + size_t(total_tiles);
         float* const before = h->d_tiles;
-        if ((rc = ensure_buffer(&h->d_tiles, &h->tiles_cap, order_words + (size_t(total_tiles) + 3) / 4))) return rc;
+        if ((rc = ensure_buffer(&h->d_tiles, &h->tiles_cap, order_words + (size_t(total_tiles) + 3) / 4, s))) return rc;
         counts = reinterpret_cast<int32_t*>(h->d_tiles);
         order = counts + 64;
         cls = reinterpret_cast<uint8_t*>(h->d_tiles + order_words);
@@ -515,7 +554,7 @@ int snerg_render(snerg_handle* h, const snerg_grid* grid, const float* mlp, cons
     if (!h) return fail(SNERG_ERR_INVALID_ARG, "handle is NULL");
     if (n_rays == 0) return SNERG_OK;
     return render_impl(h, grid, mlp, cams, n_cams, ray_ids, n_rays, opts, out_rgba, aux,
-                       static_cast<hipStream_t>(stream), h->tuning);
+                       static_cast<hipStream_t>(stream), tuning_for(h, grid, cams, n_cams, opts));
 }
 
 int snerg_render_noalloc(snerg_handle* h, const snerg_grid* grid, const float* mlp, const snerg_camera* cams,
@@ -533,7 +572,7 @@ int snerg_render_noalloc(snerg_handle* h, const snerg_grid* grid, const float* m
     if (!h) return fail(SNERG_ERR_INVALID_ARG, "handle is NULL");
     if (n_cams > kNoAllocMaxCams)
         return fail(SNERG_ERR_WORKSPACE, "snerg_render_noalloc takes at most 1024 cameras");
-    const snerg_tuning tu = h->tuning;
+    const snerg_tuning tu = tuning_for(h, grid, cams, n_cams, opts);
     int64_t tiles = 0;
     for (int32_t c = 0; c < n_cams; ++c)
         tiles += int64_t((cams[c].W + tu.tile_w - 1) / tu.tile_w) * ((cams[c].H + tu.tile_h - 1) / tu.tile_h);
@@ -625,7 +664,7 @@ int snerg_render_counted(snerg_handle* h, const snerg_grid* grid, const float* m
     if (!h) return fail(SNERG_ERR_INVALID_ARG, "handle is NULL");
     if (n_rays == 0) return SNERG_OK;
     return render_impl(h, grid, mlp, cams, n_cams, ray_ids, n_rays, opts, out_rgba, aux,
-                       static_cast<hipStream_t>(stream), h->tuning, counters);
+                       static_cast<hipStream_t>(stream), tuning_for(h, grid, cams, n_cams, opts), counters);
 }
 
 int snerg_trace_visits(snerg_handle* h, const snerg_grid* grid, const snerg_camera* cams, int32_t n_cams,
@@ -688,9 +727,9 @@ int snerg_render_backward(snerg_handle* h, const snerg_grid* grid, const float* 
     const int mlp_mode = !opts->mlp_on ? kMlpOff : ((opts->flags & SNERG_FLAG_MLP_FP16) ? kMlpF16 : kMlpF32);
     const int rows = backward_partial_rows(n_groups);
     if (mlp_mode != kMlpOff) {
-        rc = ensure_buffer(&h->d_partial, &h->partial_cap, size_t(rows) * kMlpParams);
+        rc = ensure_buffer(&h->d_partial, &h->partial_cap, size_t(rows) * kMlpParams, s);
         if (rc) return rc;
-        rc = ensure_buffer(&h->d_gcv, &h->gcv_cap, size_t(std::max<int64_t>(n_rays, 1)) * 8);
+        rc = ensure_buffer(&h->d_gcv, &h->gcv_cap, size_t(std::max<int64_t>(n_rays, 1)) * 8, s);
         if (rc) return rc;
     }
     int64_t total_tiles = 0;
@@ -934,6 +973,52 @@ int snerg_set_tuning(snerg_handle* h, const snerg_tuning* t) {
     return SNERG_OK;
 }
 
+int snerg_tuning_lookup(snerg_handle* h, const snerg_grid* grid, const snerg_camera* cams, int32_t n_cams,
+                        const snerg_opts* opts, snerg_tuning* t, int32_t* found) {
+    if (!h || !grid || !cams || n_cams < 1 || !opts || !t || !found)
+        return fail(SNERG_ERR_INVALID_ARG, "a pointer is NULL or n_cams < 1");
+    auto it = h->tuned.find(tuning_signature(grid, cams, n_cams, opts));
+    *found = it != h->tuned.end() ? 1 : 0;
+    *t = *found ? it->second : h->tuning;
+    return SNERG_OK;
+}
+
+int snerg_tuning_save(snerg_handle* h, const char* path) {
+    if (!h || !path) return fail(SNERG_ERR_INVALID_ARG, "handle/path is NULL");
+    FILE* f = std::fopen(path, "w");
+    if (!f) return fail(SNERG_ERR_INVALID_ARG, std::string("cannot write ") + path);
+    std::fprintf(f, "# snerg launch-shape cache: signature tile_w tile_h waves_per_group groups_per_cu\n");
+    for (const auto& kv : h->tuned)
+        std::fprintf(f, "%016llx %d %d %d %d\n", (unsigned long long)kv.first, kv.second.tile_w, kv.second.tile_h,
+                     kv.second.waves_per_group, kv.second.groups_per_cu);
+    const bool ok = std::fclose(f) == 0;
+    return ok ? SNERG_OK : fail(SNERG_ERR_INVALID_ARG, std::string("cannot write ") + path);
+}
+
+int snerg_tuning_load(snerg_handle* h, const char* path) {
+    if (!h || !path) return fail(SNERG_ERR_INVALID_ARG, "handle/path is NULL");
+    FILE* f = std::fopen(path, "r");
+    if (!f) return fail(SNERG_ERR_INVALID_ARG, std::string("cannot read ") + path);
+    std::vector<std::pair<uint64_t, snerg_tuning>> got;
+    char line[256];
+    int rc = SNERG_OK;
+    while (std::fgets(line, sizeof line, f)) {
+        if (line[0] == '#' || line[0] == '\n') continue;
+        unsigned long long sig = 0;
+        snerg_tuning t;
+        if (std::sscanf(line, "%llx %d %d %d %d", &sig, &t.tile_w, &t.tile_h, &t.waves_per_group, &t.groups_per_cu) != 5) {
+            rc = fail(SNERG_ERR_INVALID_ARG, std::string("malformed line in ") + path);
+            break;
+        }
+        if ((rc = check_tuning(&t))) break;
+        got.emplace_back(uint64_t(sig), t);
+    }
+    std::fclose(f);
+    if (rc) return rc;
+    for (const auto& kv : got) h->tuned[kv.first] = kv.second;
+    return SNERG_OK;
+}
+
 int snerg_get_tuning(snerg_handle* h, snerg_tuning* t) {
     if (!h || !t) return fail(SNERG_ERR_INVALID_ARG, "handle/tuning is NULL");
     *t = h->tuning;
@@ -993,6 +1078,7 @@ int snerg_autotune(snerg_handle* h, const snerg_grid* grid, const float* mlp, co
     hipEventDestroy(e1);
     if (rc) return rc;
     h->tuning = best_c;
+    h->tuned[tuning_signature(grid, cams, n_cams, opts)] = best_c;
     if (best) *best = best_c;
     if (best_ms) *best_ms = best_t;
     return render_impl(h, grid, mlp, cams, n_cams, nullptr, total, opts, out_rgba, nullptr, s, best_c);

@@ -116,6 +116,9 @@ def lib():
             "snerg_adam_step": [_P, _P, _P, _P, _P, i64, _P, _P],
             "snerg_bake_cull": [_P, i32, i32, _P, _P, i32, _P, _P, _P, _P, _P, _P],
             "snerg_bake_quantize": [_P, i32, i32, _P, _P, _P, _P, i32, _P, _P, _P, _P, _P],
+            "snerg_tuning_lookup": [_P, _P, _P, i32, _P, _P, _P],
+            "snerg_tuning_save": [_P, ctypes.c_char_p],
+            "snerg_tuning_load": [_P, ctypes.c_char_p],
             "snerg_timing_enable": [_P, i32],
             "snerg_timing_read": [_P, _P, i32, _P],
         }
@@ -135,7 +138,8 @@ EXPORTED = ["snerg_create", "snerg_destroy", "snerg_status_string", "snerg_last_
             "snerg_pack_grid", "snerg_render", "snerg_render_backward", "snerg_render_counted", "snerg_render_noalloc",
             "snerg_trace_visits",
             "snerg_set_tuning", "snerg_get_tuning", "snerg_autotune", "snerg_loss_mse", "snerg_adam_step",
-            "snerg_bake_cull", "snerg_bake_quantize", "snerg_timing_enable", "snerg_timing_read"]
+            "snerg_bake_cull", "snerg_bake_quantize", "snerg_timing_enable", "snerg_timing_read",
+            "snerg_tuning_lookup", "snerg_tuning_save", "snerg_tuning_load"]
 
 
 def _check(rc: int, what: str):
@@ -306,6 +310,23 @@ def snerg_get_tuning(handle):
     t = snerg_tuning()
     _check(lib().snerg_get_tuning(handle.h, ctypes.byref(t)), "snerg_get_tuning")
     return t.as_tuple()
+
+
+def snerg_tuning_lookup(handle, grid: snerg_grid, cams, opts):
+    """(launch shape a render of this workload uses, recorded by snerg_autotune?)"""
+    t = snerg_tuning()
+    found = ctypes.c_int32(0)
+    _check(lib().snerg_tuning_lookup(handle.h, ctypes.byref(grid), cams, len(cams), ctypes.byref(opts),
+                                     ctypes.byref(t), ctypes.byref(found)), "snerg_tuning_lookup")
+    return t.as_tuple(), bool(found.value)
+
+
+def snerg_tuning_save(handle, path):
+    _check(lib().snerg_tuning_save(handle.h, str(path).encode()), "snerg_tuning_save")
+
+
+def snerg_tuning_load(handle, path):
+    _check(lib().snerg_tuning_load(handle.h, str(path).encode()), "snerg_tuning_load")
 
 
 def snerg_autotune(handle, grid: snerg_grid, mlp, cams, opts, out_rgba, candidates=None, reps=3, stream=None):

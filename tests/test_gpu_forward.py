@@ -327,3 +327,46 @@ def test_extreme_grid_shapes(N, B, radius, fov):
     for r in range(nr):
         k = min(int(ocnt[r]), 32)
         assert np.array_equal(gv[r, :k], ovis[r, :k]), r
+
+
+def test_autotune_records_launch_shape_by_workload(tmp_path):
+    say("autotune: launch shapes recorded by workload signature, saved and loaded")
+    g, cams, mlp = tiny_case(64, 1)
+    dg = device_grid(g)
+    h = S.Handle()
+    opts = S.make_opts()
+    carr = S.make_cameras(cams)
+    other = S.make_cameras([W.orbit_camera(31, 17, seed=4)])
+    m = S.mlp_tensor(mlp)
+    n = sum(c.n_rays for c in cams)
+    out = torch.empty((n, 4), device="cuda")
+    _, found = S.snerg_tuning_lookup(h, dg.struct(), carr, opts)
+    assert not found
+    best, _ = S.snerg_autotune(h, dg.struct(), m, carr, opts, out, candidates=[(16, 4, 2, 8), (4, 16, 1, 8)], reps=1)
+    assert S.snerg_tuning_lookup(h, dg.struct(), carr, opts) == (best, True)
+    assert not S.snerg_tuning_lookup(h, dg.struct(), other, opts)[1]
+    assert not S.snerg_tuning_lookup(h, dg.struct(), carr, S.make_opts(fp16=True))[1]
+    # the handle's tuning changes renders of other workloads only
+    S.snerg_set_tuning(h, 32, 2, 1, 2)
+    assert S.snerg_tuning_lookup(h, dg.struct(), carr, opts) == (best, True)
+    assert S.snerg_tuning_lookup(h, dg.struct(), other, opts) == ((32, 2, 1, 2), False)
+    path = tmp_path / "tune.txt"
+    S.snerg_tuning_save(h, path)
+    h2 = S.Handle()
+    S.snerg_tuning_load(h2, path)
+    assert S.snerg_tuning_lookup(h2, dg.struct(), carr, opts) == (best, True)
+    # every launch shape renders the same bits
+    base = gpu_render(dg, mlp, cams)
+    S.snerg_render(h2, dg.struct(), m, carr, None, n, opts, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), base)
+    # a malformed file is rejected and adds nothing
+    bad = tmp_path / "bad.txt"
+    bad.write_text("0123 8 8 4\n")
+    h3 = S.Handle()
+    with pytest.raises(S.SnergError):
+        S.snerg_tuning_load(h3, bad)
+    assert not S.snerg_tuning_lookup(h3, dg.struct(), carr, opts)[1]
+    bad.write_text("0123 7 7 4 8\n")  # 7 x 7 is not a 64-lane tile
+    with pytest.raises(S.SnergError):
+        S.snerg_tuning_load(h3, bad)
