@@ -14,7 +14,7 @@ L'(theta) = sum_r g_r . rgba_r(theta), whose gradient is dL/dtheta by the
 chain rule.  Probes whose step flips a stopping decision or an active
 sample (the counters change) or crosses a ReLU kink (the one-sided slopes
 disagree) are replaced by others.  Bar: |g_gpu - g_fd| <= 1e-3 |g_fd| +
-1e-5 max|g_fd| per probe.
+1e-5 max|g_fd| per probe, the maximum over the probes of the same kind.
 """
 import numpy as np
 import pytest
@@ -138,9 +138,9 @@ def test_adjoint512_gradient_matches_finite_differences():
             arr.reshape(-1)[idx] = x
 
         probe(kind, cand, grad, set_g, lambda idx, arr=arr: float(arr.reshape(-1)[idx]), 16)
-    scale = max(abs(c[3]) for c in checked)
     worst = 0.0
     for kind, idx, got, want in checked:
+        scale = max(abs(c[3]) for c in checked if c[0] == kind)  # the floor is per kind of parameter
         err = abs(got - want)
         worst = max(worst, err / (1e-3 * abs(want) + 1e-5 * scale))
         assert err <= 1e-3 * abs(want) + 1e-5 * scale, (kind, idx, got, want)
