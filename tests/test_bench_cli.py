@@ -43,9 +43,13 @@ def test_algorithmic_flop_follow_the_per_unit_figures():
 def test_counter_figures_are_tied_to_the_kernel_sources():
     b = _bench()
     kv = b.committed_counters()
-    # the committed counter summary either describes these sources or is ignored
-    if kv:
-        assert kv["kernel_source_sha256"] == b.kernel_source_hash()
-        assert int(kv["traffic.plain512"]) > 0 and float(kv["copy_read_write_gbs"]) > 0
+    # a leg's counter figures are kept only while its kernel sources hash to the recorded value
+    now = b.group_hashes()
+    for k in kv:
+        if k.startswith("traffic."):
+            grp = b.LEG_GROUP[k.split(".", 1)[1]]
+            assert kv[f"sources_sha256.{grp}"] == now[grp]
+            assert int(kv[k]) > 0
     with open(b.COUNTER_SUMMARY) as f:
-        assert "kernel_source_sha256 = " in f.read()
+        text = f.read()
+    assert "sources_sha256.render = " in text and "sources_sha256.backward = " in text
