@@ -65,10 +65,12 @@ RAY_FLOP = MLP_FLOP + 36 + 9 + 7
 KERNEL_SOURCES = ("render.hip", "render_ps.hip", "backward.hip", "march.h", "mlp.h", "snerg_dev.h",
                   "snerg_launch.h", "api.cpp")  # the kernels and their launch order
 # the sources each counter figure describes: the forward render kernels, and the adjoint's
-SOURCE_GROUPS = {"render": ("render.hip", "march.h", "mlp.h", "snerg_dev.h", "snerg_launch.h"),
+SOURCE_GROUPS = {"render": ("render.hip", "render_ps.hip", "march.h", "mlp.h", "snerg_dev.h", "snerg_launch.h"),
                  "backward": ("backward.hip", "march.h", "mlp.h", "snerg_dev.h", "snerg_launch.h")}
 LEG_GROUP = {"plain512": "render", "batched1024": "render", "large1024": "render", "adjoint512_fwd": "render",
-             "adjoint512_bwd": "backward"}
+             "nondeferred_fp32": "render", "nondeferred_fp16": "render", "large1024_mb_fwd": "render",
+             "adjoint512_bwd": "backward", "adjoint512_mlp_bwd": "backward", "large1024_mb_mlp_bwd": "backward",
+             "large1024_mb_bwd": "backward", "large1024_mb_bwd_patch": "backward"}
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "counters_by_kernel.md")
 COPY_BYTES = 1 << 30
 TIMING_EVERY = 4  # frames per kernel-timed frame in the plain leg's timed region
@@ -477,7 +479,7 @@ def leg_large(args, torch, S, W, O):
         px = (r % tx)[:, None] * 8 + lane[None, :] % 8
         return (c[:, None] * (cams[0].W * cams[0].H) + py * cams[0].W + px).reshape(-1)
     batches = [patch_ids(t) for t in tiles]
-    bo[0] = S.make_opts(fp16=True, patch_rays=True)  # aligned groups of 64 neighbouring rays
+    bo[0] = S.make_opts(fp16=True)
     it[0] = 0
     ms_step_p = time_launches(train_step, 8, 2, torch)
     ms_f_p = time_launches(fwd_only, 8, 2, torch)

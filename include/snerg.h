@@ -109,11 +109,11 @@ extern "C" {
  * compositing; nothing runs per pixel.  Forward only, without aux; with
  * SNERG_FLAG_MLP_FP16 the per-sample network runs on FP16 MFMA tiles. */
 #define SNERG_FLAG_PER_SAMPLE_MLP (1u << 6)
-/* Backward with a ray list: the list comes in aligned groups of 64
- * neighbouring rays (8x8 pixel patches, as the fine-tuning patch sampler
- * draws them), so the re-march sums each wavefront's voxel gradients in LDS
- * before the device atomics, as it does for whole views.  Results are the
- * same up to float summation order; with scattered rays it is slower. */
+/* Backward with a ray list that comes in aligned groups of 64 neighbouring
+ * rays (8x8 pixel patches, as the fine-tuning patch sampler draws them).
+ * Accepted and without effect: every backward launch, whole views or any
+ * ray list, sums each wavefront's voxel gradients in LDS before the device
+ * atomics. */
 #define SNERG_FLAG_PATCH_RAYS (1u << 7)
 /* Backward: add the gradients into grad_mlp, grad_dens, grad_rgb and
  * grad_feat instead of overwriting them (gradient accumulation over

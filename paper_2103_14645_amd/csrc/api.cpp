@@ -764,7 +764,6 @@ int snerg_render_backward(snerg_handle* h, const snerg_grid* grid, const float* 
     a.tile_w = h->tuning.tile_w;
     a.tile_h = h->tuning.tile_h;
     a.mlp_only = mlp_only ? 1 : 0;
-    a.patch_rays = (opts->flags & SNERG_FLAG_PATCH_RAYS) ? 1 : 0;
     HIP_TRY(launch_backward(a, n_groups, s));
     if (mlp_mode != kMlpOff) HIP_TRY(launch_reduce_mlp(h->d_partial, rows, grad_mlp, s));
     return SNERG_OK;

@@ -360,20 +360,23 @@ struct CellWindow {
 // share most of the voxels they touch, so each voxel's eight gradient values
 // (density, RGB, features) are first summed in an open-addressed table of
 // kAggSlots entries and reach device memory with one set of atomics per
-// table flush instead of one per ray.  Keys are canonical voxel indices
-// (< 2^31; the launch falls back to direct atomics otherwise).
+// table flush instead of one per ray.  Rays of a scattered list share few
+// voxels, but the table still pays there: its flush groups each voxel's
+// adds by cache line (agg_flush), which per-lane atomics cannot.  Keys are
+// canonical voxel indices (< 2^31; the launch falls back to direct atomics
+// otherwise).
 //
 // The colour and feature sums are kept in 32-bit fixed point: on gfx950 an
 // LDS float add (ds_add_f32) retires about one lane every three cycles, an
 // LDS integer add (ds_add_u32) more than forty times faster.  A ray hands a
 // voxel its colour gradient A g_C with A = sum_k w_c(k) w_k, and the A of all
 // of a ray's hand-overs add up to at most sum_k w_k <= 1, so with
-// M = max over the wavefront's rays of |g_C|, |g_V| every hand-over value is
-// at most M and a table entry (at most 64 rays between flushes) at most 64 M.
-// Values are scaled by 2^S with M 2^S < 2^23 and rounded to integers: an
-// entry stays below 2^29 (plus its rounding), and each hand-over carries a
-// rounding error of at most 2^-24 M.  The density sums, whose size depends
-// on the grid values, stay in float.
+// M = max over the wavefront's rays of |g_C|, |g_V| all that one ray hands to
+// one voxel is at most M and a table entry (64 rays between flushes) at most
+// 64 M.  Values are scaled by 2^S, the largest power of two with M 2^S < 2^24,
+// and rounded to integers: an entry stays below 2^30 (plus its rounding),
+// and each hand-over carries a rounding error of at most 2^-24 M.  The
+// density sums, whose size depends on the grid values, stay in float.
 constexpr int kAggSlots = 512;
 constexpr int kAggLog = 9;
 constexpr int kAggProbes = 16;
@@ -395,11 +398,11 @@ struct AggTable {
 };
 
 // Fixed-point scale for a wavefront whose largest |g_C|, |g_V| is m (m >= 0,
-// the same value in every lane): 2^S with m 2^S < 2^23.
+// the same value in every lane): 2^S with m 2^S < 2^24 <= 2 m 2^S.
 __device__ __forceinline__ void agg_scale(AggTable& t, float m) {
     int e = 0;
-    (void)__builtin_frexpf(m, &e);  // m < 2^e
-    int sh = 23 - e;
+    (void)__builtin_frexpf(m, &e);  // 2^(e-1) <= m < 2^e
+    int sh = 24 - e;
     sh = m > 0.0f ? (sh < 126 ? (sh > -126 ? sh : -126) : 126) : 0;
     t.q = __builtin_ldexpf(1.0f, sh);
     t.dq = __builtin_ldexpf(1.0f, -sh);
@@ -424,13 +427,12 @@ __device__ __forceinline__ bool agg_add(const AggTable& t, int32_t key, const fl
     const uint32_t h = (uint32_t(key) * 2654435761u) >> (32 - kAggLog);
     for (int pr = 0; pr < kAggProbes; ++pr) {
         const uint32_t sl = (h + pr) & (kAggSlots - 1);
-        int32_t k = __hip_atomic_load(t.key + sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        // one round trip per probe: the compare-and-swap claims a free slot
+        // and otherwise returns the key that holds it
+        int32_t k = atomicCAS(t.key + sl, -1, key);
         if (k == -1) {
-            k = atomicCAS(t.key + sl, -1, key);
-            if (k == -1) {
-                ++fresh;
-                k = key;
-            }
+            ++fresh;
+            k = key;
         }
         if (k == key) {
             const int nv = feat ? 8 : 4;
@@ -444,26 +446,38 @@ __device__ __forceinline__ bool agg_add(const AggTable& t, int32_t key, const fl
 }
 
 // All 64 lanes together: every used entry goes to device memory, the table
-// is cleared.
-__device__ __forceinline__ void agg_flush(const BackwardArgs& a, const AggTable& t, int lane, bool feat) {
+// is cleared.  gfx950 serves a wavefront's float atomics per 64-byte line
+// (measured: about 21 G lines per second whether a line carries one lane's
+// add or sixteen), so the lanes are laid across the entries' channels, not
+// the entries: lane l takes channel l % C of entry l / C (C = 8 with
+// features, 4 without), and the four feature adds and the three colour adds
+// of a voxel each land in one line instead of seven.
+template <bool FEAT>
+__device__ __forceinline__ void agg_flush(const BackwardArgs& a, const AggTable& t, int lane) {
+    constexpr int kC = FEAT ? 8 : 4;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    for (int sl = lane; sl < kAggSlots; sl += 64) {
+    const int c = lane % kC;
+    int32_t* iv = reinterpret_cast<int32_t*>(t.val);
+    for (int sl = lane / kC; sl < kAggSlots; sl += 64 / kC) {
         const int32_t key = t.key[sl];
         if (key >= 0) {
-            float v[8];
-            int32_t* iv = reinterpret_cast<int32_t*>(t.val);
-            v[0] = t.val[sl];
-            t.val[sl] = 0.0f;
-#pragma unroll
-            for (int c = 1; c < 8; ++c) {
-                v[c] = float(iv[c * kAggSlots + sl]) * t.dq;
+            float v;
+            if (c == 0) {
+                v = t.val[sl];
+                t.val[sl] = 0.0f;
+            } else {
+                v = float(iv[c * kAggSlots + sl]) * t.dq;
                 iv[c * kAggSlots + sl] = 0;
             }
-            add_global(a, key, v, feat);
-            t.key[sl] = -1;
+            float* dst = c == 0 ? a.grad_dens + key
+                       : (c < 4 ? a.grad_rgb + 3 * int64_t(key) + (c - 1) : a.grad_feat + 4 * int64_t(key) + (c - 4));
+            if (v != 0.0f) unsafeAtomicAdd(dst, v);
         }
     }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int sl = lane; sl < kAggSlots; sl += 64) t.key[sl] = -1;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
@@ -668,7 +682,7 @@ __global__ __launch_bounds__(64 * kAggWaves) void k_march_backward(BackwardArgs 
                 in_table += wave_sum_i32(fresh);
                 fresh = 0;
                 if (in_table >= kAggFlushAt) {
-                    agg_flush(a, tab, lane, FEAT);
+                    agg_flush<FEAT>(a, tab, lane);
                     in_table = 0;
                 }
             }
@@ -678,7 +692,7 @@ __global__ __launch_bounds__(64 * kAggWaves) void k_march_backward(BackwardArgs 
 #pragma unroll
         for (int c = 0; c < 8; ++c) flush_corner<FEAT, AGG>(a, tab, win, c, gC, gV, fresh);
     }
-    if (AGG) agg_flush(a, tab, lane, FEAT);
+    if (AGG) agg_flush<FEAT>(a, tab, lane);
 }
 
 // Column sums of the [rows][883] partial-gradient matrix into out (which
@@ -716,7 +730,7 @@ hipError_t launch_backward(const BackwardArgs& a, int n_groups, hipStream_t s) {
     if (a.mlp_only) return hipSuccess;
     // aggregation keys are int32 voxel indices
     const int64_t n_vox = int64_t(a.grid.n_blocks) * a.grid.B * a.grid.B * a.grid.B;
-    const bool agg = (!a.ray_ids || a.patch_rays) && n_vox < (int64_t(1) << 31);
+    const bool agg = n_vox < (int64_t(1) << 31);
     const size_t lds = size_t(a.grid.n_words) * sizeof(uint2) + (agg ? size_t(kAggWaves) * kAggWords * 4 : 0);
     const int64_t waves = a.ray_ids ? (a.n_rays + 63) / 64 : a.total_tiles;
     const unsigned blocks = unsigned((waves + kAggWaves - 1) / kAggWaves);

@@ -58,7 +58,6 @@ struct BackwardArgs {
     int64_t total_tiles;   // tile_w x tile_h tiles over all cameras (no ray list)
     int32_t tile_w, tile_h;
     int32_t mlp_only;      // MLP gradient only: no re-march
-    int32_t patch_rays;    // ray list in groups of 64 neighbouring rays: aggregate in LDS
 };
 
 // Baking (Section 5.3, 5.4).

@@ -11,10 +11,19 @@ dL/dtheta.  For 64 sampled parameters (16 network weights, 16 densities
 with rho > 0, 16 colours, 16 features, each with a non-zero gradient) the
 FP64 oracle re-renders the minibatch at theta +- h and differentiates
 L'(theta) = sum_r g_r . rgba_r(theta), whose gradient is dL/dtheta by the
-chain rule.  Probes whose step flips a stopping decision or an active
-sample (the counters change) or crosses a ReLU kink (the one-sided slopes
-disagree) are replaced by others.  Bar: |g_gpu - g_fd| <= 1e-3 |g_fd| +
-1e-5 max|g_fd| per probe, the maximum over the probes of the same kind.
+chain rule (each ray's output is differenced before the sum over rays).
+Probes whose step flips a stopping decision or an active sample (the
+counters change) or crosses a ReLU kink (the one-sided slopes disagree)
+are replaced by others.  Bar: |g_gpu - g_fd| <= 1e-3 |g_fd| +
+1e-5 max|g_fd| per probe, the maximum over the probes of the same kind;
+colour and feature probes add the rounding the backward's LDS tables are
+built to: their fixed point rounds each hand-over of a voxel to within
+2^-24 M (M: the wavefront's largest |dL/dC_d|, |dL/dV|, at most the largest
+over the minibatch, which the FP64 network backward of the oracle's per-ray
+state gives here), and each of the H rays whose output the probe moves
+hands the voxel over at most once per sample it takes in the voxel's eight
+cells (at half-voxel steps a straight ray's path there is at most 2 sqrt(3)
+voxels long: seven samples), allowing 8 H 2^-24 M.
 """
 import numpy as np
 import pytest
@@ -24,6 +33,7 @@ import oracle as O
 import workloads as W
 from paper_2103_14645_amd import autograd as A
 from paper_2103_14645_amd import snerg as S
+from tests import fp16_reference as F
 from tests.gpu_helpers import handle, say
 
 pytestmark = pytest.mark.gpu
@@ -78,26 +88,33 @@ def test_adjoint512_gradient_matches_finite_differences():
 
     base = O.render(og, flat, cams, ray_ids=ids)
     base_cnt = base["counters"]
+    rgba0 = base["rgba"]
+    # largest per-ray |dL/dC_d|, |dL/dV| (FP64 network backward, no rounding)
+    _, gcv = F.mlp_backward_fp16(mlp, base["aux"], F.directions_of(cams, g.N, ids), g_rgba, round_operands=False)
+    m_cv = float(np.abs(gcv).max())
 
-    def lin_loss(params):
+    def rerender(params):
         res = O.render(og, params, cams, ray_ids=ids)
-        return float(np.sum(res["rgba"] * g_rgba)), res["counters"]
-
-    l0 = float(np.sum(base["rgba"] * g_rgba))
+        return res["rgba"], res["counters"]
 
     def fd(set_value, theta):
+        # Each ray's output is differenced before the sum over rays: summing
+        # L' first would leave a rounding noise of about eps |L'| / h in the
+        # quotient, as large as the smallest gradients probed here.
         hstep = 1e-6 * max(1.0, abs(theta))
         set_value(theta + hstep)
-        lp, cp = lin_loss(params_now[0])
+        rp, cp = rerender(params_now[0])
         set_value(theta - hstep)
-        lm, cm = lin_loss(params_now[0])
+        rm, cm = rerender(params_now[0])
         set_value(theta)
         if not (np.array_equal(cp, base_cnt) and np.array_equal(cm, base_cnt)):
             return None  # the step flipped a stop or an active sample
-        fwd, bwd = (lp - l0) / hstep, (l0 - lm) / hstep
+        fwd = float(np.sum((rp - rgba0) * g_rgba)) / hstep
+        bwd = float(np.sum((rgba0 - rm) * g_rgba)) / hstep
         if abs(fwd - bwd) > 1e-4 * (abs(fwd) + abs(bwd)) + 1e-12:
             return None  # the step crosses a ReLU kink
-        return (lp - lm) / (2 * hstep)
+        moved = int(np.count_nonzero(np.any(rp != rm, axis=1)))
+        return float(np.sum((rp - rm) * g_rgba)) / (2 * hstep), moved
 
     params_now = [flat]
     checked = []
@@ -110,7 +127,8 @@ def test_adjoint512_gradient_matches_finite_differences():
             v = fd(lambda x, idx=idx: set_value(idx, x), get_value(idx))
             if v is None:
                 continue
-            checked.append((kind, int(idx), float(grad.flat[idx]), v))
+            q = 8 * v[1] * 2.0 ** -24 * m_cv if kind in ("rgb", "feat") else 0.0
+            checked.append((kind, int(idx), float(grad.flat[idx]), v[0], q))
             got += 1
         assert got == want, f"too few smooth probes for {kind}"
 
@@ -139,9 +157,10 @@ def test_adjoint512_gradient_matches_finite_differences():
 
         probe(kind, cand, grad, set_g, lambda idx, arr=arr: float(arr.reshape(-1)[idx]), 16)
     worst = 0.0
-    for kind, idx, got, want in checked:
+    for kind, idx, got, want, q in checked:
         scale = max(abs(c[3]) for c in checked if c[0] == kind)  # the floor is per kind of parameter
         err = abs(got - want)
-        worst = max(worst, err / (1e-3 * abs(want) + 1e-5 * scale))
-        assert err <= 1e-3 * abs(want) + 1e-5 * scale, (kind, idx, got, want)
-    say(f"  {len(checked)} probes, worst error / bar = {worst:.3e}")
+        bar = 1e-3 * abs(want) + 1e-5 * scale + q
+        worst = max(worst, err / bar)
+        assert err <= bar, (kind, idx, got, want, q)
+    say(f"  {len(checked)} probes, worst error / bar = {worst:.3e}; largest |dL/dC_d|, |dL/dV| {m_cv:.3e}")

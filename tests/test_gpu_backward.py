@@ -85,9 +85,10 @@ def test_backward_matches_oracle_gradient(n_occ, seed, early, mlp_on, subset):
 
 @pytest.mark.parametrize("layout", ["patches", "scattered"])
 def test_patch_ray_lists_match_oracle_gradient(layout):
-    # SNERG_FLAG_PATCH_RAYS: ray lists aggregated per wavefront in LDS; exact
-    # up to summation order for any list, patch-shaped (as the fine-tuning
-    # patch sampler draws them, ragged patches included) or not
+    # ray lists aggregated per wavefront in LDS (SNERG_FLAG_PATCH_RAYS is
+    # accepted and changes nothing): exact up to summation order for any
+    # list, patch-shaped (as the fine-tuning patch sampler draws them, ragged
+    # patches included) or not
     say(f"backward with SNERG_FLAG_PATCH_RAYS, {layout} list")
     seed = 8
     g = W.tiny_grid(n_occupied=200, seed=seed)
