@@ -156,6 +156,10 @@ struct snerg_handle {
     size_t partial_cap = 0;
     float* d_gcv = nullptr;  // per-ray g_C, g_V of the backward pass
     size_t gcv_cap = 0;
+    float* d_list = nullptr;  // two-phase backward of short ray lists: listed samples
+    size_t list_cap = 0;
+    float* d_list_meta = nullptr;  // and per ray the count (int32) and the last listed k (int64)
+    size_t list_meta_cap = 0;
     float* d_tiles = nullptr;  // heavy-first tile order: counters [64], order [tiles] int32, classes [tiles] u8
     size_t tiles_cap = 0;      // in floats
     float* d_bake = nullptr;  // baking scratch: per-block max density, visibility words, atlas map
@@ -507,6 +511,8 @@ int snerg_destroy(snerg_handle* h) {
     if (h->d_counter) hipFree(h->d_counter);
     if (h->d_partial) hipFree(h->d_partial);
     if (h->d_gcv) hipFree(h->d_gcv);
+    if (h->d_list) hipFree(h->d_list);
+    if (h->d_list_meta) hipFree(h->d_list_meta);
     if (h->d_bake) hipFree(h->d_bake);
     if (h->d_tiles) hipFree(h->d_tiles);
     for (hipEvent_t e : h->t_start) hipEventDestroy(e);
@@ -764,6 +770,15 @@ int snerg_render_backward(snerg_handle* h, const snerg_grid* grid, const float* 
     a.tile_w = h->tuning.tile_w;
     a.tile_h = h->tuning.tile_h;
     a.mlp_only = mlp_only ? 1 : 0;
+    if (ray_ids && !mlp_only && n_rays <= kBackwardListMaxRays && backward_aggregates(a.grid)) {
+        rc = ensure_buffer(&h->d_list, &h->list_cap, size_t(n_rays) * kBackwardListCap * 4, s);
+        if (rc) return rc;
+        rc = ensure_buffer(&h->d_list_meta, &h->list_meta_cap, size_t(n_rays) * 4, s);
+        if (rc) return rc;
+        a.list = reinterpret_cast<int4*>(h->d_list);
+        a.list_klast = reinterpret_cast<int64_t*>(h->d_list_meta);  // [n] int64, then [n] int32
+        a.list_count = reinterpret_cast<int32_t*>(h->d_list_meta + 2 * size_t(n_rays));
+    }
     HIP_TRY(launch_backward(a, n_groups, s));
     if (mlp_mode != kMlpOff) HIP_TRY(launch_reduce_mlp(h->d_partial, rows, grad_mlp, s));
     return SNERG_OK;

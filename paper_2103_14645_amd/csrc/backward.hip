@@ -505,6 +505,186 @@ __device__ __forceinline__ void flush_corner(const BackwardArgs& a, const AggTab
     add_global(a, vi, v, FEAT);
 }
 
+// The adjoint state of one ray's re-march: its output gradient and the
+// forward's per-ray results (E, the T_N tail), the running transmittance T
+// and prefix P_k, and the corner window.  sample() takes the samples in
+// march order, as march_ray hands them over (inactive ones included), and
+// returns true once the early-stop rule ends the ray; finish() hands over
+// the last window.
+template <bool FEAT, bool AGG>
+struct AdjointRay {
+    float gC[3], gV[4];
+    float E, tail, T, Pk;
+    float delta, kx, t_stop;
+    bool early, nn_gate;
+    CellWindow win;
+    int fresh;  // this lane's new table keys since the last count
+
+    // Reads list position i's state; false when the ray composited nothing
+    // (no grid gradient) or `live` is false.
+    __device__ __forceinline__ bool setup(const BackwardArgs& a, int64_t i, bool live) {
+        float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = make_float4(0.f, 0.f, 0.f, -1.f);
+        float4 gg = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (live) {
+            a1 = reinterpret_cast<const float4*>(a.aux)[2 * i + 1];
+            live = a1.w >= 0.0f;  // nothing was composited: no grid gradient
+        }
+        gC[0] = gC[1] = gC[2] = 0.f;
+        gV[0] = gV[1] = gV[2] = gV[3] = 0.f;
+        if (live) {
+            a0 = reinterpret_cast<const float4*>(a.aux)[2 * i];
+            gg = reinterpret_cast<const float4*>(a.grad_rgba)[i];
+            gC[0] = gg.x; gC[1] = gg.y; gC[2] = gg.z;
+            if (FEAT) {
+                const float4 c0 = reinterpret_cast<const float4*>(a.gcv)[2 * i];
+                const float4 c1 = reinterpret_cast<const float4*>(a.gcv)[2 * i + 1];
+                gC[0] = c0.x; gC[1] = c0.y; gC[2] = c0.z;
+                gV[0] = c0.w; gV[1] = c1.x; gV[2] = c1.y; gV[3] = c1.z;
+            }
+        }
+        E = gC[0] * a0.x + gC[1] * a0.y + gC[2] * a0.z + (gV[0] * a0.w + gV[1] * a1.x + gV[2] * a1.y + gV[3] * a1.z);
+        const float gTN = gg.x * a.opts.bg[0] + gg.y * a.opts.bg[1] + gg.z * a.opts.bg[2] - gg.w;
+        tail = a1.w * gTN;
+        T = 1.0f;
+        Pk = 0.0f;
+        delta = 1.0f / float(a.grid.N);
+        kx = a.grid.sigma_scale * delta;
+        t_stop = a.opts.t_stop;
+        early = a.opts.early_stop != 0;
+        nn_gate = a.opts.nn_gate != 0;
+        win.rank = -1;
+        win.id = 0;
+        win.c[0] = win.c[1] = win.c[2] = 0;
+        win.b[0] = win.b[1] = win.b[2] = 0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) win.A[c] = win.D[c] = 0.0f;
+        fresh = 0;
+        return live;
+    }
+
+    // Wavefront-wide (all 64 lanes, the same value in each): the largest
+    // |g_C|, |g_V| sets the table's fixed-point scale.
+    __device__ __forceinline__ void table_scale(AggTable& tab) const {
+        float m = fmaxf(fmaxf(fabsf(gC[0]), fabsf(gC[1])), fmaxf(fabsf(gC[2]), fabsf(gV[0])));
+        m = fmaxf(m, fmaxf(fmaxf(fabsf(gV[1]), fabsf(gV[2])), fabsf(gV[3])));
+#pragma unroll
+        for (int sh = 32; sh >= 1; sh >>= 1) m = fmaxf(m, __shfl_xor(m, sh));
+        agg_scale(tab, m);  // the butterfly leaves the same maximum in every lane
+    }
+
+    __device__ __forceinline__ bool sample(const BackwardArgs& a, const AggTable& tab, int32_t rk, const uint8_t* vox,
+                                           const int32_t p[3], const int32_t fr[3]) {
+        const GridArgs& g = a.grid;
+        Sample smp;
+        gather_f32(vox, g.Bp, p, fr, smp, nn_gate);
+        if (!smp.active) return false;
+        const float e = __expf(-smp.sigma_raw * kx);
+        const float w = T * (1.0f - e);
+        const float ek = gC[0] * smp.rgb[0] + gC[1] * smp.rgb[1] + gC[2] * smp.rgb[2] +
+                         (gV[0] * smp.feat[0] + gV[1] * smp.feat[1] + gV[2] * smp.feat[2] + gV[3] * smp.feat[3]);
+        Pk += w * ek;
+        T *= e;
+        const float gsig = delta * (T * ek - (E - Pk) - tail);
+        // Slide the corner window to this sample's cell: corners on a
+        // trailing face (or all of them after a jump) are flushed once, the
+        // survivors shift to their new corner index.
+        const bool jump = win.rank != rk || abs(p[0] - win.c[0]) > 1 || abs(p[1] - win.c[1]) > 1 ||
+                          abs(p[2] - win.c[2]) > 1;
+        int dd[3] = {p[0] - win.c[0], p[1] - win.c[1], p[2] - win.c[2]};
+        uint32_t leave = 0;
+        if (jump) {
+            leave = win.rank >= 0 ? 0xFFu : 0u;
+        } else {
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                // corners with bit ax clear: 0x55, 0x33, 0x0F for ax = 0, 1, 2
+                const uint32_t clear = ax == 0 ? 0x55u : (ax == 1 ? 0x33u : 0x0Fu);
+                if (dd[ax] > 0) leave |= clear;
+                if (dd[ax] < 0) leave |= ~clear & 0xFFu;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            if ((leave >> c) & 1u) flush_corner<FEAT, AGG>(a, tab, win, c, gC, gV, fresh);
+        if (jump) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) win.A[c] = win.D[c] = 0.0f;
+            win.rank = rk;
+            win.id = g.rank_id[rk];
+            const int32_t lin = g.rank_lin[rk];
+            win.b[0] = lin % g.G;
+            win.b[1] = (lin / g.G) % g.G;
+            win.b[2] = lin / (g.G * g.G);
+            win.c[0] = p[0]; win.c[1] = p[1]; win.c[2] = p[2];
+        } else {
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                const int bit = 1 << ax;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    if (c & bit) continue;
+                    const int c1 = c | bit;
+                    const float a0v = win.A[c], d0v = win.D[c], a1v = win.A[c1], d1v = win.D[c1];
+                    win.A[c] = dd[ax] > 0 ? a1v : (dd[ax] < 0 ? 0.0f : a0v);
+                    win.D[c] = dd[ax] > 0 ? d1v : (dd[ax] < 0 ? 0.0f : d0v);
+                    win.A[c1] = dd[ax] < 0 ? a0v : (dd[ax] > 0 ? 0.0f : a1v);
+                    win.D[c1] = dd[ax] < 0 ? d0v : (dd[ax] > 0 ? 0.0f : d1v);
+                }
+                win.c[ax] += dd[ax];
+            }
+        }
+        float wc[8];
+        corner_weights(fr, wc);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            win.A[c] = fmaf(wc[c], w, win.A[c]);
+            win.D[c] = fmaf(wc[c], gsig, win.D[c]);
+        }
+        return early && T < t_stop;
+    }
+
+    __device__ __forceinline__ void finish(const BackwardArgs& a, const AggTable& tab) {
+        if (win.rank >= 0) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) flush_corner<FEAT, AGG>(a, tab, win, c, gC, gV, fresh);
+        }
+    }
+};
+
+// The table of the calling wavefront in dynamic LDS (after the occupancy
+// words), cleared.
+__device__ __forceinline__ AggTable agg_table(uint2* s_occ, int n_words, int wave, int lane, bool clear) {
+    AggTable tab;
+    int32_t* base = reinterpret_cast<int32_t*>(s_occ + n_words) + wave * kAggWords;
+    tab.key = base;
+    tab.val = reinterpret_cast<float*>(base + kAggSlots);
+    if (clear) {
+        for (int sl = lane; sl < kAggSlots; sl += 64) {
+            tab.key[sl] = -1;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) tab.val[c * kAggSlots + sl] = 0.0f;
+        }
+    }
+    return tab;
+}
+
+// Wavefront-wide, after each step of the lanes: counts the table's new keys
+// and flushes it once it is full enough.
+struct TableSync {
+    int in_table = 0;  // wave-uniform: keys in the table
+    template <bool FEAT>
+    __device__ __forceinline__ void step(const BackwardArgs& a, const AggTable& tab, int lane, int& fresh) {
+        if (__any(fresh != 0)) {
+            in_table += wave_sum_i32(fresh);
+            fresh = 0;
+            if (in_table >= kAggFlushAt) {
+                agg_flush<FEAT>(a, tab, lane);
+                in_table = 0;
+            }
+        }
+    }
+};
+
 // One lane per ray.  Without a ray list the wavefronts walk the cameras'
 // tt_w x tt_h pixel tiles (neighbouring rays, shared voxels); with a list,
 // 64 consecutive list entries.  AGG: gradients go through the per-wavefront
@@ -516,22 +696,8 @@ __global__ __launch_bounds__(64 * kAggWaves) void k_march_backward(BackwardArgs 
     for (int w = threadIdx.x; w < g.n_words; w += blockDim.x) s_occ[w] = g.occ[w];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    AggTable tab;
-    {
-        int32_t* base = reinterpret_cast<int32_t*>(s_occ + g.n_words) + wave * kAggWords;
-        tab.key = base;
-        tab.val = reinterpret_cast<float*>(base + kAggSlots);
-        if (AGG) {
-            for (int sl = lane; sl < kAggSlots; sl += 64) {
-                tab.key[sl] = -1;
-#pragma unroll
-                for (int c = 0; c < 8; ++c) tab.val[c * kAggSlots + sl] = 0.0f;
-            }
-        }
-    }
+    AggTable tab = agg_table(s_occ, g.n_words, wave, lane, AGG);
     __syncthreads();
-    const float delta = 1.0f / float(g.N);
-    const float kx = g.sigma_scale * delta;
 
     // this lane's ray: list position i (indexes aux, grad_rgba, gcv) and id r
     bool live;
@@ -554,35 +720,9 @@ __global__ __launch_bounds__(64 * kAggWaves) void k_march_backward(BackwardArgs 
             i = r = c.ray_offset + int64_t(py) * c.W + px;
         }
     }
-    float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = make_float4(0.f, 0.f, 0.f, -1.f);
-    float4 gg = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (live) {
-        a1 = reinterpret_cast<const float4*>(a.aux)[2 * i + 1];
-        live = a1.w >= 0.0f;  // nothing was composited: no grid gradient
-    }
-    float gC[3] = {0.f, 0.f, 0.f}, gV[4] = {0.f, 0.f, 0.f, 0.f};
-    if (live) {
-        a0 = reinterpret_cast<const float4*>(a.aux)[2 * i];
-        gg = reinterpret_cast<const float4*>(a.grad_rgba)[i];
-        gC[0] = gg.x; gC[1] = gg.y; gC[2] = gg.z;
-        if (FEAT) {
-            const float4 c0 = reinterpret_cast<const float4*>(a.gcv)[2 * i];
-            const float4 c1 = reinterpret_cast<const float4*>(a.gcv)[2 * i + 1];
-            gC[0] = c0.x; gC[1] = c0.y; gC[2] = c0.z;
-            gV[0] = c0.w; gV[1] = c1.x; gV[2] = c1.y; gV[3] = c1.z;
-        }
-    }
-    const float E = gC[0] * a0.x + gC[1] * a0.y + gC[2] * a0.z +
-                    (gV[0] * a0.w + gV[1] * a1.x + gV[2] * a1.y + gV[3] * a1.z);
-    const float gTN = gg.x * a.opts.bg[0] + gg.y * a.opts.bg[1] + gg.z * a.opts.bg[2] - gg.w;
-    const float tail = a1.w * gTN;
-    if (AGG) {
-        float m = fmaxf(fmaxf(fabsf(gC[0]), fabsf(gC[1])), fmaxf(fabsf(gC[2]), fabsf(gV[0])));
-        m = fmaxf(m, fmaxf(fmaxf(fabsf(gV[1]), fabsf(gV[2])), fabsf(gV[3])));
-#pragma unroll
-        for (int sh = 32; sh >= 1; sh >>= 1) m = fmaxf(m, __shfl_xor(m, sh));
-        agg_scale(tab, m);  // the butterfly leaves the same maximum in every lane
-    }
+    AdjointRay<FEAT, AGG> st;
+    live = st.setup(a, i, live);
+    if (AGG) st.table_scale(tab);
 
     int64_t o[3] = {0, 0, 0};
     int32_t s[3] = {0, 0, 1 << 15};
@@ -592,107 +732,121 @@ __global__ __launch_bounds__(64 * kAggWaves) void k_march_backward(BackwardArgs 
         float d[3];
         ray_setup(a.cams[ci], g.N, px, py, o, s, d);
     }
-
-    CellWindow win;
-    win.rank = -1;
-    win.id = 0;
-    win.c[0] = win.c[1] = win.c[2] = 0;
-    win.b[0] = win.b[1] = win.b[2] = 0;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) win.A[c] = win.D[c] = 0.0f;
-    float T = 1.0f, Pk = 0.0f;
-    int fresh = 0;    // this lane's new table keys since the last count
-    int in_table = 0; // wave-uniform: keys in the table
-    const float t_stop = a.opts.t_stop;
-    const bool early = a.opts.early_stop != 0;
-    const bool nn_gate = a.opts.nn_gate != 0;
+    TableSync sync;
     march_ray_flat_sync(
         g, s_occ, live, o, s,
         [&](int64_t, int32_t rk, const uint8_t* vox, const int32_t p[3], const int32_t fr[3]) {
-            Sample smp;
-            gather_f32(vox, g.Bp, p, fr, smp, nn_gate);
-            if (!smp.active) return false;
-            const float e = __expf(-smp.sigma_raw * kx);
-            const float w = T * (1.0f - e);
-            const float ek = gC[0] * smp.rgb[0] + gC[1] * smp.rgb[1] + gC[2] * smp.rgb[2] +
-                             (gV[0] * smp.feat[0] + gV[1] * smp.feat[1] + gV[2] * smp.feat[2] +
-                              gV[3] * smp.feat[3]);
-            Pk += w * ek;
-            T *= e;
-            const float gsig = delta * (T * ek - (E - Pk) - tail);
-            // Slide the corner window to this sample's cell: corners on a
-            // trailing face (or all of them after a jump) are flushed once,
-            // the survivors shift to their new corner index.
-            const bool jump = win.rank != rk || abs(p[0] - win.c[0]) > 1 || abs(p[1] - win.c[1]) > 1 ||
-                              abs(p[2] - win.c[2]) > 1;
-            int dd[3] = {p[0] - win.c[0], p[1] - win.c[1], p[2] - win.c[2]};
-            uint32_t leave = 0;
-            if (jump) {
-                leave = win.rank >= 0 ? 0xFFu : 0u;
-            } else {
-#pragma unroll
-                for (int ax = 0; ax < 3; ++ax) {
-                    // corners with bit ax clear: 0x55, 0x33, 0x0F for ax = 0, 1, 2
-                    const uint32_t clear = ax == 0 ? 0x55u : (ax == 1 ? 0x33u : 0x0Fu);
-                    if (dd[ax] > 0) leave |= clear;
-                    if (dd[ax] < 0) leave |= ~clear & 0xFFu;
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < 8; ++c)
-                if ((leave >> c) & 1u) flush_corner<FEAT, AGG>(a, tab, win, c, gC, gV, fresh);
-            if (jump) {
-#pragma unroll
-                for (int c = 0; c < 8; ++c) win.A[c] = win.D[c] = 0.0f;
-                win.rank = rk;
-                win.id = g.rank_id[rk];
-                const int32_t lin = g.rank_lin[rk];
-                win.b[0] = lin % g.G;
-                win.b[1] = (lin / g.G) % g.G;
-                win.b[2] = lin / (g.G * g.G);
-                win.c[0] = p[0]; win.c[1] = p[1]; win.c[2] = p[2];
-            } else {
-#pragma unroll
-                for (int ax = 0; ax < 3; ++ax) {
-                    const int bit = 1 << ax;
-#pragma unroll
-                    for (int c = 0; c < 8; ++c) {
-                        if (c & bit) continue;
-                        const int c1 = c | bit;
-                        const float a0v = win.A[c], d0v = win.D[c], a1v = win.A[c1], d1v = win.D[c1];
-                        win.A[c] = dd[ax] > 0 ? a1v : (dd[ax] < 0 ? 0.0f : a0v);
-                        win.D[c] = dd[ax] > 0 ? d1v : (dd[ax] < 0 ? 0.0f : d0v);
-                        win.A[c1] = dd[ax] < 0 ? a0v : (dd[ax] > 0 ? 0.0f : a1v);
-                        win.D[c1] = dd[ax] < 0 ? d0v : (dd[ax] > 0 ? 0.0f : d1v);
-                    }
-                    win.c[ax] += dd[ax];
-                }
-            }
-            float wc[8];
-            corner_weights(fr, wc);
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                win.A[c] = fmaf(wc[c], w, win.A[c]);
-                win.D[c] = fmaf(wc[c], gsig, win.D[c]);
-            }
-            return early && T < t_stop;
+            return st.sample(a, tab, rk, vox, p, fr);
         },
         [&]() {
-            if (AGG && __any(fresh != 0)) {
-                in_table += wave_sum_i32(fresh);
-                fresh = 0;
-                if (in_table >= kAggFlushAt) {
-                    agg_flush<FEAT>(a, tab, lane);
-                    in_table = 0;
-                }
-            }
+            if (AGG) sync.step<FEAT>(a, tab, lane, st.fresh);
             return false;
         });
-    if (win.rank >= 0) {
-#pragma unroll
-        for (int c = 0; c < 8; ++c) flush_corner<FEAT, AGG>(a, tab, win, c, gC, gV, fresh);
-    }
+    st.finish(a, tab);
     if (AGG) agg_flush<FEAT>(a, tab, lane);
+}
+
+// Short ray lists in two phases.  With few rays the wavefronts are few and
+// the backward is as slow as its slowest wavefront, whose 64 rays march in
+// lock step: at nearly every step some lane takes a sample, so every step
+// pays for the whole gradient code.  Phase 1 (k_backward_record) walks each
+// ray alone and lists the samples the walk hands over (cell position and
+// macroblock record: cells with a zero distance byte, nearly all of them
+// active; the gradient code decides); phase 2
+// (k_backward_from_list) runs the gradient code over the lists, one listed
+// sample per lane per step, with the same per-ray arithmetic in the same
+// order as k_march_backward.  A ray with more than kBackwardListCap listed
+// samples walks on from its start in phase 2, skipping the listed ones.
+constexpr int kListCap = kBackwardListCap;
+
+__global__ __launch_bounds__(256) void k_backward_record(BackwardArgs a, int4* __restrict__ list,
+                                                         int32_t* __restrict__ count, int64_t* __restrict__ klast) {
+    extern __shared__ uint2 s_occ[];
+    const GridArgs& g = a.grid;
+    for (int w = threadIdx.x; w < g.n_words; w += blockDim.x) s_occ[w] = g.occ[w];
+    __syncthreads();
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= a.n_rays) return;
+    int32_t n = 0;
+    int64_t kl = 0;
+    // rays that composited nothing have no grid gradient (phase 2 skips them)
+    if (reinterpret_cast<const float4*>(a.aux)[2 * i + 1].w >= 0.0f) {
+        int ci, px, py;
+        locate(a, a.ray_ids[i], ci, px, py);
+        int64_t o[3];
+        int32_t s[3];
+        float d[3];
+        ray_setup(a.cams[ci], g.N, px, py, o, s, d);
+        int4* mine = list + i * kListCap;
+        march_ray_flat(g, s_occ, o, s,
+                       [&](int64_t k, int32_t rk, const uint8_t*, const int32_t p[3], const int32_t fr[3]) {
+                           if (n < kListCap) {
+                               mine[n] = make_int4((p[0] << 16) | fr[0], (p[1] << 16) | fr[1], (p[2] << 16) | fr[2], rk);
+                               kl = k;
+                           }
+                           ++n;
+                           return false;
+                       });
+    }
+    count[i] = n;
+    klast[i] = kl;
+}
+
+template <bool FEAT>
+__global__ __launch_bounds__(64 * kAggWaves) void k_backward_from_list(BackwardArgs a, const int4* __restrict__ list,
+                                                                       const int32_t* __restrict__ count,
+                                                                       const int64_t* __restrict__ klast) {
+    extern __shared__ uint2 s_occ[];
+    const GridArgs& g = a.grid;
+    for (int w = threadIdx.x; w < g.n_words; w += blockDim.x) s_occ[w] = g.occ[w];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    AggTable tab = agg_table(s_occ, g.n_words, wave, lane, true);
+    __syncthreads();
+    const int64_t i = (int64_t(blockIdx.x) * kAggWaves + wave) * 64 + lane;
+    bool live = i < a.n_rays;
+    AdjointRay<FEAT, true> st;
+    live = st.setup(a, i, live);
+    st.table_scale(tab);
+    const int32_t total = live ? count[i] : 0;
+    const int32_t n = total < kListCap ? total : kListCap;
+    const int4* mine = list + i * kListCap;
+    TableSync sync;
+    bool going = live;
+    for (int32_t j = 0; __any(going && j < n); ++j) {
+        if (going && j < n) {
+            const int4 e = mine[j];
+            const int32_t p[3] = {e.x >> 16, e.y >> 16, e.z >> 16};
+            const int32_t fr[3] = {e.x & 0xFFFF, e.y & 0xFFFF, e.z & 0xFFFF};
+            const uint8_t* vox = g.rec + int64_t(e.w) * g.rec_stride + g.dist_bytes;
+            if (st.sample(a, tab, e.w, vox, p, fr)) going = false;
+        }
+        sync.step<FEAT>(a, tab, lane, st.fresh);
+    }
+    // past the list: walk from the start and take the samples after the last listed one
+    const bool more = going && total > kListCap;
+    if (__any(more)) {
+        int64_t o[3] = {0, 0, 0};
+        int32_t s[3] = {0, 0, 1 << 15};
+        const int64_t k_listed = more ? klast[i] : 0;
+        if (more) {
+            int ci, px, py;
+            locate(a, a.ray_ids[i], ci, px, py);
+            float d[3];
+            ray_setup(a.cams[ci], g.N, px, py, o, s, d);
+        }
+        march_ray_flat_sync(
+            g, s_occ, more, o, s,
+            [&](int64_t k, int32_t rk, const uint8_t* vox, const int32_t p[3], const int32_t fr[3]) {
+                return k > k_listed && st.sample(a, tab, rk, vox, p, fr);
+            },
+            [&]() {
+                sync.step<FEAT>(a, tab, lane, st.fresh);
+                return false;
+            });
+    }
+    st.finish(a, tab);
+    agg_flush<FEAT>(a, tab, lane);
 }
 
 // Column sums of the [rows][883] partial-gradient matrix into out (which
@@ -717,6 +871,10 @@ __global__ __launch_bounds__(256) void k_reduce_rows(const float* __restrict__ p
 
 int backward_partial_rows(int n_groups) { return n_groups * kBwdWaves; }
 
+bool backward_aggregates(const GridArgs& g) {
+    return int64_t(g.n_blocks) * g.B * g.B * g.B < (int64_t(1) << 31);
+}
+
 hipError_t launch_backward(const BackwardArgs& a, int n_groups, hipStream_t s) {
     if (a.n_rays <= 0) return hipSuccess;
     hipError_t e;
@@ -730,11 +888,25 @@ hipError_t launch_backward(const BackwardArgs& a, int n_groups, hipStream_t s) {
     if (a.mlp_only) return hipSuccess;
     // aggregation keys are int32 voxel indices
     const int64_t n_vox = int64_t(a.grid.n_blocks) * a.grid.B * a.grid.B * a.grid.B;
-    const bool agg = n_vox < (int64_t(1) << 31);
+    const bool agg = backward_aggregates(a.grid);
     const size_t lds = size_t(a.grid.n_words) * sizeof(uint2) + (agg ? size_t(kAggWaves) * kAggWords * 4 : 0);
     const int64_t waves = a.ray_ids ? (a.n_rays + 63) / 64 : a.total_tiles;
     const unsigned blocks = unsigned((waves + kAggWaves - 1) / kAggWaves);
     const bool feat = a.mlp_mode != kMlpOff;
+    (void)n_vox;
+    if (a.list) {  // short ray list: record, then the gradient from the lists
+        const size_t occ = size_t(a.grid.n_words) * sizeof(uint2);
+        hipLaunchKernelGGL(k_backward_record, dim3(unsigned((a.n_rays + 255) / 256)), dim3(256), occ, s, a, a.list,
+                           a.list_count, a.list_klast);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (feat)
+            hipLaunchKernelGGL(k_backward_from_list<true>, dim3(blocks), dim3(64 * kAggWaves), lds, s, a, a.list,
+                               a.list_count, a.list_klast);
+        else
+            hipLaunchKernelGGL(k_backward_from_list<false>, dim3(blocks), dim3(64 * kAggWaves), lds, s, a, a.list,
+                               a.list_count, a.list_klast);
+        return hipGetLastError();
+    }
     if (feat && agg)
         hipLaunchKernelGGL((k_march_backward<true, true>), dim3(blocks), dim3(64 * kAggWaves), lds, s, a);
     else if (feat)

@@ -58,7 +58,17 @@ struct BackwardArgs {
     int64_t total_tiles;   // tile_w x tile_h tiles over all cameras (no ray list)
     int32_t tile_w, tile_h;
     int32_t mlp_only;      // MLP gradient only: no re-march
+    // short ray lists, two phases (null: one re-march): per list entry
+    // kBackwardListCap listed samples, the count and the last listed k
+    int4* list;
+    int32_t* list_count;
+    int64_t* list_klast;
 };
+
+// The two-phase backward serves ray lists of at most kBackwardListMaxRays
+// rays (few wavefronts, so the slowest one sets the time).
+constexpr int kBackwardListCap = 512;
+constexpr int64_t kBackwardListMaxRays = int64_t(1) << 18;
 
 // Baking (Section 5.3, 5.4).
 struct BakeCullPlan {
@@ -113,6 +123,8 @@ constexpr int kCostClasses = 16;
 hipError_t launch_tile_order(const RenderArgs& a, uint8_t* cls, int32_t* counts, int32_t* order, hipStream_t s);
 hipError_t launch_backward(const BackwardArgs& a, int n_groups, hipStream_t s);
 int backward_partial_rows(int n_groups);
+// Gradient aggregation in LDS needs int32 voxel keys (fewer than 2^31 voxels).
+bool backward_aggregates(const GridArgs& g);
 hipError_t launch_render_ps(const RenderArgs& a, int vt, bool f16, int wpg, int n_groups, hipStream_t s);
 hipError_t launch_mse(const float* rgba, const float* target, const int64_t* ids, int64_t n, float* grad, float* loss,
                       hipStream_t s);
