@@ -479,7 +479,7 @@ def leg_large(args, torch, S, W, O):
         px = (r % tx)[:, None] * 8 + lane[None, :] % 8
         return (c[:, None] * (cams[0].W * cams[0].H) + py * cams[0].W + px).reshape(-1)
     batches = [patch_ids(t) for t in tiles]
-    bo[0] = S.make_opts(fp16=True)
+    bo[0] = S.make_opts(fp16=True, patch_rays=True)  # aligned groups of 64 neighbouring rays
     it[0] = 0
     ms_step_p = time_launches(train_step, 8, 2, torch)
     ms_f_p = time_launches(fwd_only, 8, 2, torch)

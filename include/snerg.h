@@ -110,10 +110,12 @@ extern "C" {
  * SNERG_FLAG_MLP_FP16 the per-sample network runs on FP16 MFMA tiles. */
 #define SNERG_FLAG_PER_SAMPLE_MLP (1u << 6)
 /* Backward with a ray list that comes in aligned groups of 64 neighbouring
- * rays (8x8 pixel patches, as the fine-tuning patch sampler draws them).
- * Accepted and without effect: every backward launch, whole views or any
- * ray list, sums each wavefront's voxel gradients in LDS before the device
- * atomics. */
+ * rays (8x8 pixel patches, as the fine-tuning patch sampler draws them):
+ * each wavefront's rays share voxels, so their gradients are summed per
+ * voxel in LDS before the device atomics, as for whole views.  Without it a
+ * ray list's gradients pass through an LDS log (no summing; faster when
+ * rays share little).  Results are the same up to float summation order
+ * either way. */
 #define SNERG_FLAG_PATCH_RAYS (1u << 7)
 /* Backward: add the gradients into grad_mlp, grad_dens, grad_rgb and
  * grad_feat instead of overwriting them (gradient accumulation over

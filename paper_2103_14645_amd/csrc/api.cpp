@@ -770,6 +770,7 @@ int snerg_render_backward(snerg_handle* h, const snerg_grid* grid, const float* 
     a.tile_w = h->tuning.tile_w;
     a.tile_h = h->tuning.tile_h;
     a.mlp_only = mlp_only ? 1 : 0;
+    a.patch_rays = (opts->flags & SNERG_FLAG_PATCH_RAYS) ? 1 : 0;
     if (ray_ids && !mlp_only && n_rays <= kBackwardListMaxRays && backward_aggregates(a.grid)) {
         rc = ensure_buffer(&h->d_list, &h->list_cap, size_t(n_rays) * kBackwardListCap * 4, s);
         if (rc) return rc;

@@ -360,11 +360,8 @@ struct CellWindow {
 // share most of the voxels they touch, so each voxel's eight gradient values
 // (density, RGB, features) are first summed in an open-addressed table of
 // kAggSlots entries and reach device memory with one set of atomics per
-// table flush instead of one per ray.  Rays of a scattered list share few
-// voxels, but the table still pays there: its flush groups each voxel's
-// adds by cache line (agg_flush), which per-lane atomics cannot.  Keys are
-// canonical voxel indices (< 2^31; the launch falls back to direct atomics
-// otherwise).
+// table flush instead of one per ray.  Keys are canonical voxel indices
+// (< 2^31; the launch falls back to direct atomics otherwise).
 //
 // The colour and feature sums are kept in 32-bit fixed point: on gfx950 an
 // LDS float add (ds_add_f32) retires about one lane every three cycles, an
@@ -389,13 +386,23 @@ constexpr int kAggProbes = 16;
 constexpr int kAggFlushAt = kAggSlots * 7 / 8;
 constexpr int kAggWaves = 4;                 // wavefronts per workgroup
 constexpr int kAggWords = kAggSlots * 9;     // keys, 8 value planes
+// dynamic LDS of the re-march kernels: occupancy words, kAggWaves tables,
+// one log counter per wavefront
+constexpr int kAggLdsWords = kAggWaves * kAggWords + kAggWaves;
 
 struct AggTable {
     int32_t* key;  // [kAggSlots], -1 = free
     float* val;    // [8][kAggSlots]: plane 0 float (density), planes 1..7 int32 fixed point
     float q;       // wave-uniform 2^S: fixed-point scale of the colour and feature planes
     float dq;      // 2^-S
+    int32_t* cnt;  // as a log (see log_add): entries written
 };
+
+// The same LDS as an append-only log, for rays that share few voxels
+// (scattered ray lists): entry e holds a key and its eight float values,
+// written once; no probing and no LDS atomics per value, one counter bump
+// per wavefront and corner.  Flushed by cache line as the table is.
+constexpr int kLogFlushAt = kAggSlots - 192;
 
 // Fixed-point scale for a wavefront whose largest |g_C|, |g_V| is m (m >= 0,
 // the same value in every lane): 2^S with m 2^S < 2^24 <= 2 m 2^S.
@@ -445,6 +452,48 @@ __device__ __forceinline__ bool agg_add(const AggTable& t, int32_t key, const fl
     return false;
 }
 
+// Appends (key, v) to the log (lanes may diverge: the calling lanes share one
+// counter bump); false when the log is full.
+__device__ __forceinline__ bool log_add(const AggTable& t, int32_t key, const float v[8], bool feat) {
+    const uint64_t m = __ballot(1);
+    const int lane = threadIdx.x & 63;
+    const int leader = __builtin_ctzll(m);
+    const int rank = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+    int base = 0;
+    if (lane == leader) base = atomicAdd(t.cnt, __builtin_popcountll(m));
+    base = __shfl(base, leader);
+    const int e = base + rank;
+    if (e >= kAggSlots) return false;
+    t.key[e] = key;
+    const int nv = feat ? 8 : 4;
+    for (int c = 0; c < nv; ++c) t.val[c * kAggSlots + e] = v[c];
+    return true;
+}
+
+// All 64 lanes together: the log's entries go to device memory (lanes
+// across channels, as in agg_flush) and the log is emptied.
+template <bool FEAT>
+__device__ __forceinline__ void log_flush(const BackwardArgs& a, const AggTable& t, int lane) {
+    constexpr int kC = FEAT ? 8 : 4;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    int n = __builtin_amdgcn_readfirstlane(*t.cnt);
+    n = n < kAggSlots ? n : kAggSlots;
+    const int c = lane % kC;
+    for (int e = lane / kC; e < n; e += 64 / kC) {
+        const int32_t key = t.key[e];
+        const float v = t.val[c * kAggSlots + e];
+        float* dst = c == 0 ? a.grad_dens + key
+                   : (c < 4 ? a.grad_rgb + 3 * int64_t(key) + (c - 1) : a.grad_feat + 4 * int64_t(key) + (c - 4));
+        if (v != 0.0f) unsafeAtomicAdd(dst, v);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) *t.cnt = 0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // All 64 lanes together: every used entry goes to device memory, the table
 // is cleared.  gfx950 serves a wavefront's float atomics per 64-byte line
 // (measured: about 21 G lines per second whether a line carries one lane's
@@ -488,7 +537,7 @@ __device__ __forceinline__ int wave_sum_i32(int v) {
     return __builtin_amdgcn_readfirstlane(v);
 }
 
-template <bool FEAT, bool AGG>
+template <bool FEAT, bool AGG, bool LOG>
 __device__ __forceinline__ void flush_corner(const BackwardArgs& a, const AggTable& t, const CellWindow& w, int c,
                                              const float gC[3], const float gV[4], int& fresh) {
     const float A = w.A[c], D = w.D[c];
@@ -501,7 +550,11 @@ __device__ __forceinline__ void flush_corner(const BackwardArgs& a, const AggTab
     if (FEAT) {
         v[4] = A * gV[0]; v[5] = A * gV[1]; v[6] = A * gV[2]; v[7] = A * gV[3];
     }
-    if (AGG && agg_add(t, int32_t(vi), v, FEAT, fresh)) return;
+    if (LOG) {
+        if (log_add(t, int32_t(vi), v, FEAT)) return;
+    } else if (AGG && agg_add(t, int32_t(vi), v, FEAT, fresh)) {
+        return;
+    }
     add_global(a, vi, v, FEAT);
 }
 
@@ -511,7 +564,7 @@ __device__ __forceinline__ void flush_corner(const BackwardArgs& a, const AggTab
 // march order, as march_ray hands them over (inactive ones included), and
 // returns true once the early-stop rule ends the ray; finish() hands over
 // the last window.
-template <bool FEAT, bool AGG>
+template <bool FEAT, bool AGG, bool LOG = false>
 struct AdjointRay {
     float gC[3], gV[4];
     float E, tail, T, Pk;
@@ -605,7 +658,7 @@ struct AdjointRay {
         }
 #pragma unroll
         for (int c = 0; c < 8; ++c)
-            if ((leave >> c) & 1u) flush_corner<FEAT, AGG>(a, tab, win, c, gC, gV, fresh);
+            if ((leave >> c) & 1u) flush_corner<FEAT, AGG, LOG>(a, tab, win, c, gC, gV, fresh);
         if (jump) {
 #pragma unroll
             for (int c = 0; c < 8; ++c) win.A[c] = win.D[c] = 0.0f;
@@ -646,7 +699,7 @@ struct AdjointRay {
     __device__ __forceinline__ void finish(const BackwardArgs& a, const AggTable& tab) {
         if (win.rank >= 0) {
 #pragma unroll
-            for (int c = 0; c < 8; ++c) flush_corner<FEAT, AGG>(a, tab, win, c, gC, gV, fresh);
+            for (int c = 0; c < 8; ++c) flush_corner<FEAT, AGG, LOG>(a, tab, win, c, gC, gV, fresh);
         }
     }
 };
@@ -658,7 +711,9 @@ __device__ __forceinline__ AggTable agg_table(uint2* s_occ, int n_words, int wav
     int32_t* base = reinterpret_cast<int32_t*>(s_occ + n_words) + wave * kAggWords;
     tab.key = base;
     tab.val = reinterpret_cast<float*>(base + kAggSlots);
-    if (clear) {
+    tab.cnt = reinterpret_cast<int32_t*>(s_occ + n_words) + kAggWaves * kAggWords + wave;
+    if (clear) {  // (the LDS exists only then)
+        if (lane == 0) *tab.cnt = 0;
         for (int sl = lane; sl < kAggSlots; sl += 64) {
             tab.key[sl] = -1;
 #pragma unroll
@@ -672,6 +727,10 @@ __device__ __forceinline__ AggTable agg_table(uint2* s_occ, int n_words, int wav
 // and flushes it once it is full enough.
 struct TableSync {
     int in_table = 0;  // wave-uniform: keys in the table
+    template <bool FEAT>
+    __device__ __forceinline__ void log_step(const BackwardArgs& a, const AggTable& tab, int lane) {
+        if (__builtin_amdgcn_readfirstlane(*tab.cnt) >= kLogFlushAt) log_flush<FEAT>(a, tab, lane);
+    }
     template <bool FEAT>
     __device__ __forceinline__ void step(const BackwardArgs& a, const AggTable& tab, int lane, int& fresh) {
         if (__any(fresh != 0)) {
@@ -792,7 +851,7 @@ __global__ __launch_bounds__(256) void k_backward_record(BackwardArgs a, int4* _
     klast[i] = kl;
 }
 
-template <bool FEAT>
+template <bool FEAT, bool LOG>
 __global__ __launch_bounds__(64 * kAggWaves) void k_backward_from_list(BackwardArgs a, const int4* __restrict__ list,
                                                                        const int32_t* __restrict__ count,
                                                                        const int64_t* __restrict__ klast) {
@@ -805,9 +864,9 @@ __global__ __launch_bounds__(64 * kAggWaves) void k_backward_from_list(BackwardA
     __syncthreads();
     const int64_t i = (int64_t(blockIdx.x) * kAggWaves + wave) * 64 + lane;
     bool live = i < a.n_rays;
-    AdjointRay<FEAT, true> st;
+    AdjointRay<FEAT, true, LOG> st;
     live = st.setup(a, i, live);
-    st.table_scale(tab);
+    if (!LOG) st.table_scale(tab);
     const int32_t total = live ? count[i] : 0;
     const int32_t n = total < kListCap ? total : kListCap;
     const int4* mine = list + i * kListCap;
@@ -821,7 +880,8 @@ __global__ __launch_bounds__(64 * kAggWaves) void k_backward_from_list(BackwardA
             const uint8_t* vox = g.rec + int64_t(e.w) * g.rec_stride + g.dist_bytes;
             if (st.sample(a, tab, e.w, vox, p, fr)) going = false;
         }
-        sync.step<FEAT>(a, tab, lane, st.fresh);
+        if (LOG) sync.log_step<FEAT>(a, tab, lane);
+        else sync.step<FEAT>(a, tab, lane, st.fresh);
     }
     // past the list: walk from the start and take the samples after the last listed one
     const bool more = going && total > kListCap;
@@ -841,12 +901,14 @@ __global__ __launch_bounds__(64 * kAggWaves) void k_backward_from_list(BackwardA
                 return k > k_listed && st.sample(a, tab, rk, vox, p, fr);
             },
             [&]() {
-                sync.step<FEAT>(a, tab, lane, st.fresh);
+                if (LOG) sync.log_step<FEAT>(a, tab, lane);
+                else sync.step<FEAT>(a, tab, lane, st.fresh);
                 return false;
             });
     }
     st.finish(a, tab);
-    agg_flush<FEAT>(a, tab, lane);
+    if (LOG) log_flush<FEAT>(a, tab, lane);
+    else agg_flush<FEAT>(a, tab, lane);
 }
 
 // Column sums of the [rows][883] partial-gradient matrix into out (which
@@ -889,7 +951,7 @@ hipError_t launch_backward(const BackwardArgs& a, int n_groups, hipStream_t s) {
     // aggregation keys are int32 voxel indices
     const int64_t n_vox = int64_t(a.grid.n_blocks) * a.grid.B * a.grid.B * a.grid.B;
     const bool agg = backward_aggregates(a.grid);
-    const size_t lds = size_t(a.grid.n_words) * sizeof(uint2) + (agg ? size_t(kAggWaves) * kAggWords * 4 : 0);
+    const size_t lds = size_t(a.grid.n_words) * sizeof(uint2) + (agg ? size_t(kAggLdsWords) * 4 : 0);
     const int64_t waves = a.ray_ids ? (a.n_rays + 63) / 64 : a.total_tiles;
     const unsigned blocks = unsigned((waves + kAggWaves - 1) / kAggWaves);
     const bool feat = a.mlp_mode != kMlpOff;
@@ -899,12 +961,19 @@ hipError_t launch_backward(const BackwardArgs& a, int n_groups, hipStream_t s) {
         hipLaunchKernelGGL(k_backward_record, dim3(unsigned((a.n_rays + 255) / 256)), dim3(256), occ, s, a, a.list,
                            a.list_count, a.list_klast);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (feat)
-            hipLaunchKernelGGL(k_backward_from_list<true>, dim3(blocks), dim3(64 * kAggWaves), lds, s, a, a.list,
-                               a.list_count, a.list_klast);
+        // scattered rays share few voxels: the log; patches: the aggregating table
+        if (feat && a.patch_rays)
+            hipLaunchKernelGGL((k_backward_from_list<true, false>), dim3(blocks), dim3(64 * kAggWaves), lds, s, a,
+                               a.list, a.list_count, a.list_klast);
+        else if (feat)
+            hipLaunchKernelGGL((k_backward_from_list<true, true>), dim3(blocks), dim3(64 * kAggWaves), lds, s, a,
+                               a.list, a.list_count, a.list_klast);
+        else if (a.patch_rays)
+            hipLaunchKernelGGL((k_backward_from_list<false, false>), dim3(blocks), dim3(64 * kAggWaves), lds, s, a,
+                               a.list, a.list_count, a.list_klast);
         else
-            hipLaunchKernelGGL(k_backward_from_list<false>, dim3(blocks), dim3(64 * kAggWaves), lds, s, a, a.list,
-                               a.list_count, a.list_klast);
+            hipLaunchKernelGGL((k_backward_from_list<false, true>), dim3(blocks), dim3(64 * kAggWaves), lds, s, a,
+                               a.list, a.list_count, a.list_klast);
         return hipGetLastError();
     }
     if (feat && agg)

@@ -58,6 +58,7 @@ struct BackwardArgs {
     int64_t total_tiles;   // tile_w x tile_h tiles over all cameras (no ray list)
     int32_t tile_w, tile_h;
     int32_t mlp_only;      // MLP gradient only: no re-march
+    int32_t patch_rays;    // ray list in groups of 64 neighbouring rays
     // short ray lists, two phases (null: one re-march): per list entry
     // kBackwardListCap listed samples, the count and the last listed k
     int4* list;

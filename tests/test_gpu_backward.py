@@ -83,13 +83,14 @@ def test_backward_matches_oracle_gradient(n_occ, seed, early, mlp_on, subset):
     assert np.abs(out - ref).max() <= 1e-4
 
 
-@pytest.mark.parametrize("layout", ["patches", "scattered"])
-def test_patch_ray_lists_match_oracle_gradient(layout):
-    # ray lists aggregated per wavefront in LDS (SNERG_FLAG_PATCH_RAYS is
-    # accepted and changes nothing): exact up to summation order for any
-    # list, patch-shaped (as the fine-tuning patch sampler draws them, ragged
+@pytest.mark.parametrize("layout,patch", [("patches", True), ("scattered", True), ("scattered", False),
+                                          ("patches", False)])
+def test_patch_ray_lists_match_oracle_gradient(layout, patch):
+    # ray lists with SNERG_FLAG_PATCH_RAYS (gradients summed per wavefront in
+    # LDS) or without (an LDS log): exact up to summation order for any list,
+    # patch-shaped (as the fine-tuning patch sampler draws them, ragged
     # patches included) or not
-    say(f"backward with SNERG_FLAG_PATCH_RAYS, {layout} list")
+    say(f"backward of a {layout} list, SNERG_FLAG_PATCH_RAYS={patch}")
     seed = 8
     g = W.tiny_grid(n_occupied=200, seed=seed)
     vals = shadow_values(g, seed)
@@ -108,8 +109,45 @@ def test_patch_ray_lists_match_oracle_gradient(layout):
     og = O.OracleGrid(g, values=vals)
     ids = stable_ids(og, mlp, cams, ids)
     g_rgba = rng.normal(size=(len(ids), 4)) / len(ids)
-    gm, gd, gr, gf, out = run_backward(g, vals, mlp, cams, g_rgba, ids=ids, patch_rays=True)
+    gm, gd, gr, gf, out = run_backward(g, vals, mlp, cams, g_rgba, ids=ids, patch_rays=patch)
     om, od, orr, of = O.render_grad(og, mlp, cams, g_rgba, ray_ids=ids)
+    compare("mlp", gm, om)
+    compare("dens", gd, od)
+    compare("rgb", gr, orr)
+    compare("feat", gf, of)
+
+
+@pytest.mark.parametrize("patch", [False, True])
+def test_long_rays_past_the_sample_list(patch):
+    # A ray list's backward lists up to 512 samples per ray before its
+    # gradient pass; longer rays walk on from their start past the listed
+    # ones.  Rays along a fully occupied column of 16 macroblocks (512
+    # voxels, about 1,024 samples each) take that path; the whole frame and a
+    # list of its rays against the oracle, early stop off.
+    N, B = 512, 32
+    G = N // B
+    ind = np.full(G ** 3, -1, np.int32)
+    for bx in range(G):
+        ind[(8 * G + 8) * G + bx] = bx
+    rng = np.random.default_rng(12)
+    dens = rng.integers(3, 9, (G, B, B, B), dtype=np.uint8)  # nowhere zero (also after the shadow's +-0.01)
+    rgb = rng.integers(0, 256, (G, B, B, B, 3), dtype=np.uint8)
+    feat = rng.integers(0, 256, (G, B, B, B, 4), dtype=np.uint8)
+    g = W.Grid(N, B, ind, dens, rgb, feat)
+    fwd, up = np.array([1.0, 0.0, 0.0]), np.array([0.0, 0.0, 1.0])
+    y, z = (8 * B + 16.25) * 2.0 / N - 1.0, (8 * B + 15.75) * 2.0 / N - 1.0
+    cams = [W.Camera(np.array([-2.5, y, z]), fwd, np.cross(fwd, up), up, 12, 10, 3000.0)]
+    vals = shadow_values(g, 12)
+    mlp = W.mlp_weights(13)
+    og = O.OracleGrid(g, values=vals)
+    n = cams[0].n_rays
+    cnt = O.render(og, mlp, cams, early_stop=False)["counters"]
+    say(f"long rays: composited samples per ray {int(cnt[:, 3].min())}..{int(cnt[:, 3].max())}")
+    assert cnt[:, 3].min() > 600  # every ray overflows the 512-sample list
+    ids = np.random.default_rng(3).permutation(n)[: n - 7]
+    g_rgba = rng.normal(size=(len(ids), 4)) / len(ids)
+    gm, gd, gr, gf, _ = run_backward(g, vals, mlp, cams, g_rgba, ids=ids, early_stop=False, patch_rays=patch)
+    om, od, orr, of = O.render_grad(og, mlp, cams, g_rgba, ray_ids=ids, early_stop=False)
     compare("mlp", gm, om)
     compare("dens", gd, od)
     compare("rgb", gr, orr)
