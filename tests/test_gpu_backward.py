@@ -154,6 +154,30 @@ def test_long_rays_past_the_sample_list(patch):
     compare("feat", gf, of)
 
 
+@pytest.mark.parametrize("patch", [False, True])
+def test_long_ray_list_single_remarch(patch):
+    # Lists longer than 2^18 rays take the single re-march (one lane per
+    # ray, gradients summed in the LDS table), not the two phases.
+    seed = 14
+    g = W.tiny_grid(n_occupied=120, seed=seed)
+    vals = shadow_values(g, seed)
+    mlp = W.mlp_weights(seed + 1)
+    cams = [W.orbit_camera(640, 480, seed=seed + 2)]
+    n = cams[0].n_rays
+    rng = np.random.default_rng(seed)
+    og = O.OracleGrid(g, values=vals)
+    ids = stable_ids(og, mlp, cams, rng.permutation(n)[: (1 << 18) + 4097])
+    assert len(ids) > (1 << 18)
+    say(f"backward of a {len(ids)}-ray list, SNERG_FLAG_PATCH_RAYS={patch}")
+    g_rgba = rng.normal(size=(len(ids), 4)) / len(ids)
+    gm, gd, gr, gf, _ = run_backward(g, vals, mlp, cams, g_rgba, ids=ids, patch_rays=patch)
+    om, od, orr, of = O.render_grad(og, mlp, cams, g_rgba, ray_ids=ids)
+    compare("mlp", gm, om)
+    compare("dens", gd, od)
+    compare("rgb", gr, orr)
+    compare("feat", gf, of)
+
+
 def test_mse_step_reduces_loss():
     say("autograd: one SGD step on an MSE against perturbed targets lowers the loss")
     g = W.tiny_grid(n_occupied=96, seed=4)
