@@ -761,7 +761,7 @@ __global__ __launch_bounds__(64 * kAggWaves) void k_march_backward(BackwardArgs 
     // this lane's ray: list position i (indexes aux, grad_rgba, gcv) and id r
     bool live;
     int64_t i, r;
-    const int64_t wt = int64_t(blockIdx.x) * kAggWaves + wave;
+    const int64_t wt = int64_t(a.ray_ids ? blockIdx.x : xcd_grouped(blockIdx.x, gridDim.x)) * kAggWaves + wave;
     if (a.ray_ids) {
         i = wt * 64 + lane;
         live = i < a.n_rays;

@@ -190,7 +190,7 @@ __global__ __launch_bounds__(256) void k_render(RenderArgs a) {
     // One inlined copy of the per-ray body; the launch modes differ only in
     // how a wavefront obtains its next 64 rays (wave-uniform control flow).
     int64_t t = a.mode == kModeList ? int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63)
-                                    : int64_t(blockIdx.x) * wpg + wave;
+                                    : int64_t(xcd_grouped(blockIdx.x, gridDim.x)) * wpg + wave;
     for (;;) {
         if (PERSIST) {
             int64_t v = 0;

@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void k_render_ps(RenderArgs a) {
     const bool nn_gate = a.opts.nn_gate != 0;
     const bool persist = a.mode == kModePersistent;
     int64_t t = a.mode == kModeList ? int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63)
-                                    : int64_t(blockIdx.x) * wpg + wave;
+                                    : int64_t(xcd_grouped(blockIdx.x, gridDim.x)) * wpg + wave;
     for (;;) {
         if (persist) {
             int64_t v = 0;

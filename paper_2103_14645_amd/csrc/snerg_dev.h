@@ -220,6 +220,20 @@ __host__ __device__ __forceinline__ int32_t block_steps(const int32_t P[3], cons
     return n;
 }
 
+// Workgroup w of a launch of n goes to XCD w mod 8 (each of the eight XCDs
+// has its own L2), so consecutive workgroups of a tile order, which render
+// neighbouring tiles and read the same macroblocks, would land in eight
+// different L2s.  This permutation of [0, n) gives each XCD runs of 8
+// consecutive workgroups while the XCDs still advance through the order
+// together; the last n mod 64 stay in place.  Only the speed depends on the
+// dispatch order, never the result.
+__device__ __forceinline__ uint32_t xcd_grouped(uint32_t w, uint32_t n) {
+    constexpr uint32_t kRun = 8, kChunk = 8 * kRun;
+    if (w >= n / kChunk * kChunk) return w;
+    const uint32_t r = w % kChunk;
+    return w - r + (r % 8) * kRun + r / 8;
+}
+
 // Camera of a global tile / ray index (binary search over the table).
 __device__ __forceinline__ int find_camera_by_tile(const DevCamera* cams, int n, int64_t t) {
     int lo = 0, hi = n - 1;
