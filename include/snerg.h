@@ -221,8 +221,14 @@ int snerg_render(snerg_handle *h, const snerg_grid *grid, const float *mlp, cons
  * is stored); aux must come from snerg_render of the same rays, grid, MLP,
  * cameras and options.  grad_rgba: device [n_rays][4].  Outputs (device,
  * overwritten, or added to with SNERG_FLAG_ACCUMULATE): grad_mlp [883],
- * grad_dens, grad_rgb, grad_feat in canonical atlas layout.  Gradient sums use float32 atomics,
- * so their rounding depends on scheduling.  With SNERG_FLAG_MLP_FP16 the MLP
+ * grad_dens, grad_rgb, grad_feat in canonical atlas layout.  Gradient sums
+ * use float32 atomics, so their rounding depends on scheduling; where a
+ * wavefront's rays are summed per voxel in LDS first (whole views, and ray
+ * lists with SNERG_FLAG_PATCH_RAYS) the colour and feature sums are 32-bit
+ * fixed point, each hand-over rounded to within 2^-24 of the wavefront's
+ * largest |dL/dC_d|, |dL/dV|.  A ray list of at most 2^18 rays runs in two
+ * phases whose per-ray sample lists (up to 8 KB per ray) live in
+ * handle-owned device memory, kept for later calls.  With SNERG_FLAG_MLP_FP16 the MLP
  * backward runs on FP16 MFMA tiles with FP32 accumulation (as the forward).
  * With SNERG_FLAG_MLP_GRAD_ONLY only grad_mlp is computed (the fine-tuning
  * of Section 5.5 optimises the deferred network alone): no ray is
