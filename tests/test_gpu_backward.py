@@ -178,6 +178,55 @@ def test_long_ray_list_single_remarch(patch):
     compare("feat", gf, of)
 
 
+@pytest.mark.parametrize("patch", [False, True])
+def test_small_and_empty_ray_lists(patch):
+    # A one-ray list, a list of rays that miss the grid or composite nothing
+    # (their gradients are zero), a ragged 65-ray list, and a zero-ray call
+    # (it clears the outputs, or leaves them with SNERG_FLAG_ACCUMULATE).
+    seed = 15
+    g = W.tiny_grid(n_occupied=64, seed=seed)
+    vals = shadow_values(g, seed)
+    mlp = W.mlp_weights(seed + 1)
+    cams = [W.orbit_camera(32, 24, seed=seed + 2)]
+    og = O.OracleGrid(g, values=vals)
+    base = O.render(og, mlp, cams)
+    composited = base["counters"][:, 3]
+    hit = np.flatnonzero(composited > 0)
+    miss = np.flatnonzero(composited == 0)
+    assert len(hit) > 65 and len(miss) > 8
+    rng = np.random.default_rng(seed)
+    for name, ids in (("one ray", hit[:1]), ("nothing composited", miss[:40]),
+                      ("65 rays", rng.permutation(hit)[:65])):
+        ids = stable_ids(og, mlp, cams, np.asarray(ids))
+        say(f"  list of {len(ids)} rays ({name}), SNERG_FLAG_PATCH_RAYS={patch}")
+        g_rgba = rng.normal(size=(len(ids), 4)) / max(len(ids), 1)
+        gm, gd, gr, gf, _ = run_backward(g, vals, mlp, cams, g_rgba, ids=ids, patch_rays=patch)
+        om, od, orr, of = O.render_grad(og, mlp, cams, g_rgba, ray_ids=ids)
+        if name == "nothing composited":
+            assert not (gd.any() or gr.any() or gf.any())
+        compare("mlp", gm, om)
+        compare("dens", gd, od)
+        compare("rgb", gr, orr)
+        compare("feat", gf, of)
+    # zero rays
+    h = handle()
+    r = A.ShadowRenderer(h, g.N, g.B, g.indirection, g.n_blocks)
+    dens, rgb, feat = (torch.from_numpy(v).cuda() for v in vals)
+    r.pack(dens, rgb, feat)
+    carr = S.make_cameras(cams)
+    idt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    empty4 = torch.zeros((1, 4), device="cuda")
+    aux = torch.zeros((1, 8), device="cuda")
+    for acc in (False, True):
+        gm = torch.full((883,), 7.0, device="cuda")
+        gd, gr, gf = (torch.full_like(x, 7.0) for x in (dens, rgb, feat))
+        S.snerg_render_backward(h, r.struct(), S.mlp_tensor(mlp), carr, idt, 0,
+                                S.make_opts(accumulate=acc, patch_rays=patch), aux, empty4, gm, gd, gr, gf)
+        torch.cuda.synchronize()
+        want = 7.0 if acc else 0.0
+        assert all(bool((x == want).all()) for x in (gm, gd, gr, gf)), acc
+
+
 def test_mse_step_reduces_loss():
     say("autograd: one SGD step on an MSE against perturbed targets lowers the loss")
     g = W.tiny_grid(n_occupied=96, seed=4)
