@@ -386,23 +386,20 @@ constexpr int kAggProbes = 16;
 constexpr int kAggFlushAt = kAggSlots * 7 / 8;
 constexpr int kAggWaves = 4;                 // wavefronts per workgroup
 constexpr int kAggWords = kAggSlots * 9;     // keys, 8 value planes
-// dynamic LDS of the re-march kernels: occupancy words, kAggWaves tables,
-// one log counter per wavefront
-constexpr int kAggLdsWords = kAggWaves * kAggWords + kAggWaves;
+// dynamic LDS of the re-march kernels after the occupancy words: kAggWaves tables
+constexpr int kAggLdsWords = kAggWaves * kAggWords;
 
 struct AggTable {
     int32_t* key;  // [kAggSlots], -1 = free
     float* val;    // [8][kAggSlots]: plane 0 float (density), planes 1..7 int32 fixed point
     float q;       // wave-uniform 2^S: fixed-point scale of the colour and feature planes
     float dq;      // 2^-S
-    int32_t* cnt;  // as a log (see log_add): entries written
 };
 
 // The same LDS as an append-only log, for rays that share few voxels
 // (scattered ray lists): entry e holds a key and its eight float values,
-// written once; no probing and no LDS atomics per value, one counter bump
-// per wavefront and corner.  Flushed by cache line as the table is.
-constexpr int kLogFlushAt = kAggSlots - 192;
+// written once, with no probing and no LDS atomics (AdjointRay::commit
+// places the entries).  Flushed by cache line as the table is.
 
 // Fixed-point scale for a wavefront whose largest |g_C|, |g_V| is m (m >= 0,
 // the same value in every lane): 2^S with m 2^S < 2^24 <= 2 m 2^S.
@@ -452,44 +449,30 @@ __device__ __forceinline__ bool agg_add(const AggTable& t, int32_t key, const fl
     return false;
 }
 
-// Appends (key, v) to the log (lanes may diverge: the calling lanes share one
-// counter bump); false when the log is full.
-__device__ __forceinline__ bool log_add(const AggTable& t, int32_t key, const float v[8], bool feat) {
-    const uint64_t m = __ballot(1);
-    const int lane = threadIdx.x & 63;
-    const int leader = __builtin_ctzll(m);
-    const int rank = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
-    int base = 0;
-    if (lane == leader) base = atomicAdd(t.cnt, __builtin_popcountll(m));
-    base = __shfl(base, leader);
-    const int e = base + rank;
-    if (e >= kAggSlots) return false;
-    t.key[e] = key;
-    const int nv = feat ? 8 : 4;
-    for (int c = 0; c < nv; ++c) t.val[c * kAggSlots + e] = v[c];
-    return true;
+// The device address of channel c (0 density, 1..3 RGB, 4..7 features) of
+// voxel key.
+__device__ __forceinline__ float* grad_channel(const BackwardArgs& a, int32_t key, int c) {
+    return c == 0 ? a.grad_dens + key
+                  : (c < 4 ? a.grad_rgb + 3 * int64_t(key) + (c - 1) : a.grad_feat + 4 * int64_t(key) + (c - 4));
 }
 
-// All 64 lanes together: the log's entries go to device memory (lanes
-// across channels, as in agg_flush) and the log is emptied.
+// All 64 lanes together: the log's first n entries go to device memory and
+// the log is emptied.  Lanes are laid across each entry's channels as in
+// agg_flush.
 template <bool FEAT>
-__device__ __forceinline__ void log_flush(const BackwardArgs& a, const AggTable& t, int lane) {
-    constexpr int kC = FEAT ? 8 : 4;
+__device__ __forceinline__ void log_flush(const BackwardArgs& a, const AggTable& t, int lane, int n) {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    int n = __builtin_amdgcn_readfirstlane(*t.cnt);
-    n = n < kAggSlots ? n : kAggSlots;
-    const int c = lane % kC;
-    for (int e = lane / kC; e < n; e += 64 / kC) {
+    const int c = lane & 3;
+    for (int e = lane >> 2; e < n; e += 16) {
         const int32_t key = t.key[e];
-        const float v = t.val[c * kAggSlots + e];
-        float* dst = c == 0 ? a.grad_dens + key
-                   : (c < 4 ? a.grad_rgb + 3 * int64_t(key) + (c - 1) : a.grad_feat + 4 * int64_t(key) + (c - 4));
-        if (v != 0.0f) unsafeAtomicAdd(dst, v);
+        const float v0 = t.val[c * kAggSlots + e];
+        if (v0 != 0.0f) unsafeAtomicAdd(grad_channel(a, key, c), v0);
+        if (FEAT) {
+            const float v1 = t.val[(c + 4) * kAggSlots + e];
+            if (v1 != 0.0f) unsafeAtomicAdd(grad_channel(a, key, c + 4), v1);
+        }
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    if (lane == 0) *t.cnt = 0;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
@@ -498,30 +481,33 @@ __device__ __forceinline__ void log_flush(const BackwardArgs& a, const AggTable&
 // is cleared.  gfx950 serves a wavefront's float atomics per 64-byte line
 // (measured: about 21 G lines per second whether a line carries one lane's
 // add or sixteen), so the lanes are laid across the entries' channels, not
-// the entries: lane l takes channel l % C of entry l / C (C = 8 with
-// features, 4 without), and the four feature adds and the three colour adds
-// of a voxel each land in one line instead of seven.
+// the entries: lane l takes entry l / 4 of a group of 16 and within it
+// channels l % 4 and l % 4 + 4, so that one instruction adds an entry's
+// density and colour (two lines) and the next its four features (one
+// line), where one lane per entry would touch seven lines.
 template <bool FEAT>
 __device__ __forceinline__ void agg_flush(const BackwardArgs& a, const AggTable& t, int lane) {
-    constexpr int kC = FEAT ? 8 : 4;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    const int c = lane % kC;
+    const int c = lane & 3;
     int32_t* iv = reinterpret_cast<int32_t*>(t.val);
-    for (int sl = lane / kC; sl < kAggSlots; sl += 64 / kC) {
+    for (int sl = lane >> 2; sl < kAggSlots; sl += 16) {
         const int32_t key = t.key[sl];
         if (key >= 0) {
-            float v;
+            float v0;
             if (c == 0) {
-                v = t.val[sl];
+                v0 = t.val[sl];
                 t.val[sl] = 0.0f;
             } else {
-                v = float(iv[c * kAggSlots + sl]) * t.dq;
+                v0 = float(iv[c * kAggSlots + sl]) * t.dq;
                 iv[c * kAggSlots + sl] = 0;
             }
-            float* dst = c == 0 ? a.grad_dens + key
-                       : (c < 4 ? a.grad_rgb + 3 * int64_t(key) + (c - 1) : a.grad_feat + 4 * int64_t(key) + (c - 4));
-            if (v != 0.0f) unsafeAtomicAdd(dst, v);
+            if (v0 != 0.0f) unsafeAtomicAdd(grad_channel(a, key, c), v0);
+            if (FEAT) {
+                const float v1 = float(iv[(c + 4) * kAggSlots + sl]) * t.dq;
+                iv[(c + 4) * kAggSlots + sl] = 0;
+                if (v1 != 0.0f) unsafeAtomicAdd(grad_channel(a, key, c + 4), v1);
+            }
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -537,7 +523,7 @@ __device__ __forceinline__ int wave_sum_i32(int v) {
     return __builtin_amdgcn_readfirstlane(v);
 }
 
-template <bool FEAT, bool AGG, bool LOG>
+template <bool FEAT, bool AGG>
 __device__ __forceinline__ void flush_corner(const BackwardArgs& a, const AggTable& t, const CellWindow& w, int c,
                                              const float gC[3], const float gV[4], int& fresh) {
     const float A = w.A[c], D = w.D[c];
@@ -550,11 +536,7 @@ __device__ __forceinline__ void flush_corner(const BackwardArgs& a, const AggTab
     if (FEAT) {
         v[4] = A * gV[0]; v[5] = A * gV[1]; v[6] = A * gV[2]; v[7] = A * gV[3];
     }
-    if (LOG) {
-        if (log_add(t, int32_t(vi), v, FEAT)) return;
-    } else if (AGG && agg_add(t, int32_t(vi), v, FEAT, fresh)) {
-        return;
-    }
+    if (AGG && agg_add(t, int32_t(vi), v, FEAT, fresh)) return;
     add_global(a, vi, v, FEAT);
 }
 
@@ -572,6 +554,10 @@ struct AdjointRay {
     bool early, nn_gate;
     CellWindow win;
     int fresh;  // this lane's new table keys since the last count
+    // LOG: the corners handed over since the last commit, by corner index
+    uint32_t pmask;
+    int32_t pvi[8];
+    float pA[8], pD[8];
 
     // Reads list position i's state; false when the ray composited nothing
     // (no grid gradient) or `live` is false.
@@ -612,7 +598,59 @@ struct AdjointRay {
 #pragma unroll
         for (int c = 0; c < 8; ++c) win.A[c] = win.D[c] = 0.0f;
         fresh = 0;
+        pmask = 0;
         return live;
+    }
+
+    // LOG: keeps corner c's hand-over (lanes may diverge) for commit().
+    __device__ __forceinline__ void stash(const GridArgs& g, int c) {
+        const float A = win.A[c], D = win.D[c];
+        if (A == 0.0f && D == 0.0f) return;
+        const int64_t vi = canonical_voxel(g, win.id, win.b, win.c[0] + (c & 1) - 1, win.c[1] + ((c >> 1) & 1) - 1,
+                                           win.c[2] + (c >> 2) - 1);
+        if (vi < 0) return;
+        pvi[c] = int32_t(vi);  // LOG runs only on grids of fewer than 2^31 voxels
+        pA[c] = A;
+        pD[c] = D;
+        pmask |= 1u << c;
+    }
+
+    // LOG, all 64 lanes together: appends the stashed hand-overs to the log,
+    // corner by corner.  The lanes appending a corner take the next entries
+    // in lane order (a ballot and a prefix count), so the fill count n stays
+    // the same in every lane and nothing needs an LDS atomic; the log is
+    // flushed whenever another corner might not fit.
+    template <bool F>
+    __device__ __forceinline__ void commit(const BackwardArgs& a, const AggTable& t, int lane, int& n) {
+        const GridArgs& g = a.grid;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const bool want = (pmask >> c) & 1u;
+            const uint64_t m = __ballot(want);
+            if (m == 0) continue;  // wave-uniform
+            if (n > kAggSlots - 64) {
+                log_flush<F>(a, t, lane, n);
+                n = 0;
+            }
+            if (want) {
+                const int e = n + int(__builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)));
+                const float A = pA[c];
+                t.key[e] = pvi[c];
+                t.val[e] = g.sigma_scale * pD[c];
+                t.val[kAggSlots + e] = A * gC[0];
+                t.val[2 * kAggSlots + e] = A * gC[1];
+                t.val[3 * kAggSlots + e] = A * gC[2];
+                if (F) {
+                    t.val[4 * kAggSlots + e] = A * gV[0];
+                    t.val[5 * kAggSlots + e] = A * gV[1];
+                    t.val[6 * kAggSlots + e] = A * gV[2];
+                    t.val[7 * kAggSlots + e] = A * gV[3];
+                }
+            }
+            n += __builtin_popcountll(m);
+        }
+        pmask = 0;
     }
 
     // Wavefront-wide (all 64 lanes, the same value in each): the largest
@@ -658,7 +696,10 @@ struct AdjointRay {
         }
 #pragma unroll
         for (int c = 0; c < 8; ++c)
-            if ((leave >> c) & 1u) flush_corner<FEAT, AGG, LOG>(a, tab, win, c, gC, gV, fresh);
+            if ((leave >> c) & 1u) {
+                if (LOG) stash(g, c);
+                else flush_corner<FEAT, AGG>(a, tab, win, c, gC, gV, fresh);
+            }
         if (jump) {
 #pragma unroll
             for (int c = 0; c < 8; ++c) win.A[c] = win.D[c] = 0.0f;
@@ -699,7 +740,10 @@ struct AdjointRay {
     __device__ __forceinline__ void finish(const BackwardArgs& a, const AggTable& tab) {
         if (win.rank >= 0) {
 #pragma unroll
-            for (int c = 0; c < 8; ++c) flush_corner<FEAT, AGG, LOG>(a, tab, win, c, gC, gV, fresh);
+            for (int c = 0; c < 8; ++c) {
+                if (LOG) stash(a.grid, c);
+                else flush_corner<FEAT, AGG>(a, tab, win, c, gC, gV, fresh);
+            }
         }
     }
 };
@@ -711,9 +755,7 @@ __device__ __forceinline__ AggTable agg_table(uint2* s_occ, int n_words, int wav
     int32_t* base = reinterpret_cast<int32_t*>(s_occ + n_words) + wave * kAggWords;
     tab.key = base;
     tab.val = reinterpret_cast<float*>(base + kAggSlots);
-    tab.cnt = reinterpret_cast<int32_t*>(s_occ + n_words) + kAggWaves * kAggWords + wave;
-    if (clear) {  // (the LDS exists only then)
-        if (lane == 0) *tab.cnt = 0;
+    if (clear) {
         for (int sl = lane; sl < kAggSlots; sl += 64) {
             tab.key[sl] = -1;
 #pragma unroll
@@ -727,10 +769,6 @@ __device__ __forceinline__ AggTable agg_table(uint2* s_occ, int n_words, int wav
 // and flushes it once it is full enough.
 struct TableSync {
     int in_table = 0;  // wave-uniform: keys in the table
-    template <bool FEAT>
-    __device__ __forceinline__ void log_step(const BackwardArgs& a, const AggTable& tab, int lane) {
-        if (__builtin_amdgcn_readfirstlane(*tab.cnt) >= kLogFlushAt) log_flush<FEAT>(a, tab, lane);
-    }
     template <bool FEAT>
     __device__ __forceinline__ void step(const BackwardArgs& a, const AggTable& tab, int lane, int& fresh) {
         if (__any(fresh != 0)) {
@@ -871,16 +909,20 @@ __global__ __launch_bounds__(64 * kAggWaves) void k_backward_from_list(BackwardA
     const int32_t n = total < kListCap ? total : kListCap;
     const int4* mine = list + i * kListCap;
     TableSync sync;
+    int n_log = 0;  // LOG: entries in the log, the same in every lane
     bool going = live;
+    // the next entry is read one step ahead, off the step's chain of loads
+    int4 e_next = n > 0 ? mine[0] : make_int4(0, 0, 0, 0);
     for (int32_t j = 0; __any(going && j < n); ++j) {
+        const int4 e = e_next;
+        if (going && j + 1 < n) e_next = mine[j + 1];
         if (going && j < n) {
-            const int4 e = mine[j];
             const int32_t p[3] = {e.x >> 16, e.y >> 16, e.z >> 16};
             const int32_t fr[3] = {e.x & 0xFFFF, e.y & 0xFFFF, e.z & 0xFFFF};
             const uint8_t* vox = g.rec + int64_t(e.w) * g.rec_stride + g.dist_bytes;
             if (st.sample(a, tab, e.w, vox, p, fr)) going = false;
         }
-        if (LOG) sync.log_step<FEAT>(a, tab, lane);
+        if (LOG) st.template commit<FEAT>(a, tab, lane, n_log);
         else sync.step<FEAT>(a, tab, lane, st.fresh);
     }
     // past the list: walk from the start and take the samples after the last listed one
@@ -901,14 +943,18 @@ __global__ __launch_bounds__(64 * kAggWaves) void k_backward_from_list(BackwardA
                 return k > k_listed && st.sample(a, tab, rk, vox, p, fr);
             },
             [&]() {
-                if (LOG) sync.log_step<FEAT>(a, tab, lane);
+                if (LOG) st.template commit<FEAT>(a, tab, lane, n_log);
                 else sync.step<FEAT>(a, tab, lane, st.fresh);
                 return false;
             });
     }
     st.finish(a, tab);
-    if (LOG) log_flush<FEAT>(a, tab, lane);
-    else agg_flush<FEAT>(a, tab, lane);
+    if (LOG) {
+        st.template commit<FEAT>(a, tab, lane, n_log);
+        log_flush<FEAT>(a, tab, lane, n_log);
+    } else {
+        agg_flush<FEAT>(a, tab, lane);
+    }
 }
 
 // Column sums of the [rows][883] partial-gradient matrix into out (which
