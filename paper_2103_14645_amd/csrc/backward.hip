@@ -665,9 +665,15 @@ struct AdjointRay {
 
     __device__ __forceinline__ bool sample(const BackwardArgs& a, const AggTable& tab, int32_t rk, const uint8_t* vox,
                                            const int32_t p[3], const int32_t fr[3]) {
-        const GridArgs& g = a.grid;
         Sample smp;
-        gather_f32(vox, g.Bp, p, fr, smp, nn_gate);
+        gather_f32(vox, a.grid.Bp, p, fr, smp, nn_gate);
+        return take(a, tab, rk, smp, p, fr);
+    }
+
+    // The sample with its corners already interpolated.
+    __device__ __forceinline__ bool take(const BackwardArgs& a, const AggTable& tab, int32_t rk, const Sample& smp,
+                                         const int32_t p[3], const int32_t fr[3]) {
+        const GridArgs& g = a.grid;
         if (!smp.active) return false;
         const float e = __expf(-smp.sigma_raw * kx);
         const float w = T * (1.0f - e);
@@ -911,19 +917,41 @@ __global__ __launch_bounds__(64 * kAggWaves) void k_backward_from_list(BackwardA
     TableSync sync;
     int n_log = 0;  // LOG: entries in the log, the same in every lane
     bool going = live;
-    // the next entry is read one step ahead, off the step's chain of loads
-    int4 e_next = n > 0 ? mine[0] : make_int4(0, 0, 0, 0);
-    for (int32_t j = 0; __any(going && j < n); ++j) {
-        const int4 e = e_next;
-        if (going && j + 1 < n) e_next = mine[j + 1];
+    // Software pipeline (at these sizes one wavefront per SIMD, so nothing
+    // else hides a step's loads): list entries are read two steps ahead and
+    // the next sample's corners are loaded before the current sample's
+    // gradient work, in two corner buffers with the loop unrolled by two so
+    // that neither is copied.
+    const int4 none = make_int4(0, 0, 0, 0);
+    int4 e0 = n > 0 ? mine[0] : none;
+    int4 e1 = n > 1 ? mine[1] : none;
+    CornersF32 cb[2];
+    auto load = [&](const int4& e, CornersF32& cn) {
+        const int32_t p[3] = {e.x >> 16, e.y >> 16, e.z >> 16};
+        load_corners_f32(g.rec + int64_t(e.w) * g.rec_stride + g.dist_bytes, g.Bp, p, cn);
+    };
+    if (n > 0) load(e0, cb[0]);
+    auto step = [&](int32_t j, const int4& e, const CornersF32& cn) {
         if (going && j < n) {
             const int32_t p[3] = {e.x >> 16, e.y >> 16, e.z >> 16};
             const int32_t fr[3] = {e.x & 0xFFFF, e.y & 0xFFFF, e.z & 0xFFFF};
-            const uint8_t* vox = g.rec + int64_t(e.w) * g.rec_stride + g.dist_bytes;
-            if (st.sample(a, tab, e.w, vox, p, fr)) going = false;
+            Sample smp;
+            interp_f32(cn, fr, smp, st.nn_gate);
+            if (st.take(a, tab, e.w, smp, p, fr)) going = false;
         }
         if (LOG) st.template commit<FEAT>(a, tab, lane, n_log);
         else sync.step<FEAT>(a, tab, lane, st.fresh);
+    };
+    for (int32_t j = 0; __any(going && j < n); j += 2) {
+        if (going && j + 1 < n) load(e1, cb[1]);
+        const int4 e2 = going && j + 2 < n ? mine[j + 2] : none;
+        step(j, e0, cb[0]);
+        if (!__any(going && j + 1 < n)) break;
+        if (going && j + 2 < n) load(e2, cb[0]);
+        const int4 e3 = going && j + 3 < n ? mine[j + 3] : none;
+        step(j + 1, e1, cb[1]);
+        e0 = e2;
+        e1 = e3;
     }
     // past the list: walk from the start and take the samples after the last listed one
     const bool more = going && total > kListCap;

@@ -120,6 +120,48 @@ __device__ __forceinline__ void gather_u8(const uint8_t* __restrict__ blk, int B
     interp_u8(cn, fr, smp);
 }
 
+// The 8 corners of a padded cell of a float32 block (32 bytes per voxel:
+// density, RGB, features), loaded by load_corners_f32 and sampled by
+// interp_f32: gather_f32 in two parts, so that a caller can issue the loads
+// of its next sample before it works on the current one.
+struct CornersF32 {
+    float4 a[8], b[8];
+};
+
+__device__ __forceinline__ void load_corners_f32(const uint8_t* __restrict__ blk, int Bp, const int32_t p[3],
+                                                 CornersF32& cn) {
+    const float4* base = reinterpret_cast<const float4*>(blk) + (int64_t((p[2] * Bp + p[1]) * Bp + p[0]) << 1);
+    const int sy = Bp * 2, sz = Bp * Bp * 2;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const float4* q = base + ((c & 4) ? sz : 0) + ((c & 2) ? sy : 0) + ((c & 1) ? 2 : 0);
+        cn.a[c] = q[0];
+        cn.b[c] = q[1];
+    }
+}
+
+// The same arithmetic in the same order as gather_f32.
+__device__ __forceinline__ void interp_f32(const CornersF32& cn, const int32_t fr[3], Sample& smp, bool nn_gate) {
+    float w[8];
+    corner_weights(fr, w);
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    bool act = false;
+    const int cnn = nearest_corner(fr);
+    float dnn = 0.f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const float4 a = cn.a[c], b = cn.b[c];
+        act |= (a.x != 0.f) && corner_live(c, fr);
+        dnn = c == cnn ? a.x : dnn;
+        acc[0] += w[c] * a.x; acc[1] += w[c] * a.y; acc[2] += w[c] * a.z; acc[3] += w[c] * a.w;
+        acc[4] += w[c] * b.x; acc[5] += w[c] * b.y; acc[6] += w[c] * b.z; acc[7] += w[c] * b.w;
+    }
+    smp.sigma_raw = acc[0];
+    smp.rgb[0] = acc[1]; smp.rgb[1] = acc[2]; smp.rgb[2] = acc[3];
+    smp.feat[0] = acc[4]; smp.feat[1] = acc[5]; smp.feat[2] = acc[6]; smp.feat[3] = acc[7];
+    smp.active = nn_gate ? dnn != 0.f : act;
+}
+
 // Gather at padded cell p of a float32 block (32 bytes per voxel).
 // With nn_gate the sample counts as active only when the nearest corner's
 // density is non-zero (the WebGL renderer's test; that corner always has
