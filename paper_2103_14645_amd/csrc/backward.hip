@@ -16,8 +16,15 @@
 //     w_c(k) a corner voxel receives sum_k w_c(k) dL/dsigma_k (density) and
 //     g_C, g_V times A = sum_k w_c(k) w_k (colour, features).  Along one ray
 //     each cell coordinate is monotone, so the 8 corners of the current cell
-//     are kept as running (A, D) sums and a voxel is flushed to the gradient
-//     arrays (float atomics) once, when the ray's cell window leaves it.
+//     are kept as running (A, D) sums and a voxel is handed over once, when
+//     the ray's cell window leaves it: into a per-wavefront LDS table that
+//     sums the hand-overs of the wavefront's rays (whole views in 8x8 pixel
+//     tiles, patch lists), or an LDS log (scattered ray lists), flushed to
+//     the gradient arrays with float atomics grouped by cache line.
+//  Short ray lists (up to 2^18 rays) run K2 in two phases: k_backward_record
+//     lists each ray's samples, k_backward_from_list runs the same adjoint
+//     over the lists (the single re-march is as slow as its slowest
+//     wavefront when the wavefronts are few).
 #include "march.h"
 #include "mlp.h"
 #include "snerg_launch.h"
@@ -379,7 +386,7 @@ constexpr int kAggLog = 9;
 constexpr int kAggProbes = 16;
 // Flush once this many keys are in.  Every flush sends each held voxel's
 // eight sums to device memory as float atomics, which gfx950 executes at the
-// memory side at a few tens of G per second, so the fewer flushes the
+// memory side, about 21 G cache lines per second, so the fewer flushes the
 // better: at 7/8 full the adjoint frame runs 18% faster than at 1/2 (the
 // table then holds most of a tile's voxels at once); a key that finds no
 // free slot within kAggProbes probes goes to device memory directly.
