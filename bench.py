@@ -447,13 +447,14 @@ def leg_large(args, torch, S, W, O):
     gout = torch.randn((mb, 4), device="cuda") / mb
     gm = torch.empty(883, device="cuda")
     gd, gr, gf = torch.empty_like(dens), torch.empty_like(rgb), torch.empty_like(feat)
+    grads = [(gd, gr, gf)]
     it = [0]
 
     def train_step():
         b = batches[it[0] % len(batches)]
         it[0] += 1
         S.snerg_render(h, sgrid, m, carr, b, mb, bo[0], bout, aux)
-        S.snerg_render_backward(h, sgrid, m, carr, b, mb, bo[0], aux, gout, gm, gd, gr, gf)
+        S.snerg_render_backward(h, sgrid, m, carr, b, mb, bo[0], aux, gout, gm, *grads[0])
 
     def fwd_only():
         b = batches[it[0] % len(batches)]
@@ -468,6 +469,14 @@ def leg_large(args, torch, S, W, O):
     bo[0] = S.make_opts(fp16=True, accumulate=True)
     gm.zero_(); gd.zero_(); gr.zero_(); gf.zero_()
     ms_step_acc = time_launches(train_step, 8, 2, torch)
+    # the same with the grid gradients packed per voxel (SNERG_FLAG_GRAD_PACKED):
+    # one cache line of device atomics per voxel hand-over instead of three
+    grads[0] = (torch.zeros((dens.numel(), 8), device="cuda"), None, None)
+    bo[0] = S.make_opts(fp16=True, grad_packed=True)
+    ms_step_pk = time_launches(train_step, 8, 2, torch)
+    bo[0] = S.make_opts(fp16=True, grad_packed=True, accumulate=True)
+    ms_step_pk_acc = time_launches(train_step, 8, 2, torch)
+    grads[0] = (gd, gr, gf)
     bo[0] = S.make_opts(fp16=True)
     # the same with minibatches of 1,024 whole 8x8 patches drawn across the 64 views
     tx, ty = cams[0].W // 8, cams[0].H // 8
@@ -488,11 +497,16 @@ def leg_large(args, torch, S, W, O):
                mb=mb, cpu_mrays=cpu_mrays,
                ms_train_step=ms_step, ms_mb_fwd=ms_f, bwd_mrays=mb / ms_b / 1e3,
                ms_train_step_accumulate=ms_step_acc, bwd_mrays_accumulate=mb / max(ms_step_acc - ms_f, 1e-6) / 1e3,
+               ms_train_step_packed=ms_step_pk, bwd_mrays_packed=mb / max(ms_step_pk - ms_f, 1e-6) / 1e3,
+               ms_train_step_packed_accumulate=ms_step_pk_acc,
+               bwd_mrays_packed_accumulate=mb / max(ms_step_pk_acc - ms_f, 1e-6) / 1e3,
                ms_train_step_patches=ms_step_p, ms_mb_fwd_patches=ms_f_p,
                bwd_mrays_patches=mb / max(ms_step_p - ms_f_p, 1e-6) / 1e3)
     log(f"large1024: {ms:.1f} ms/launch, {res['mrays']:.1f} Mrays/s, fp16 err {err:.2e}; minibatch fwd+bwd "
         f"{ms_step:.2f} ms (bwd {res['bwd_mrays']:.1f} Mrays/s; accumulating {ms_step_acc:.2f} ms, bwd "
-        f"{res['bwd_mrays_accumulate']:.1f} Mrays/s); as 8x8 patches {ms_step_p:.2f} ms "
+        f"{res['bwd_mrays_accumulate']:.1f} Mrays/s); packed gradients {ms_step_pk:.2f} ms (bwd "
+        f"{res['bwd_mrays_packed']:.1f} Mrays/s; accumulating {ms_step_pk_acc:.2f} ms, bwd "
+        f"{res['bwd_mrays_packed_accumulate']:.1f} Mrays/s); as 8x8 patches {ms_step_p:.2f} ms "
         f"(bwd {res['bwd_mrays_patches']:.1f} Mrays/s)")
     return res
 
@@ -832,6 +846,10 @@ def main():
                                   "bwd_mrays": round(b["bwd_mrays"], 3), "cpu_oracle_mrays": round(b["cpu_mrays"], 4),
                                   "ms_minibatch_fwd_bwd_accumulate": round(b["ms_train_step_accumulate"], 4),
                                   "bwd_mrays_accumulate": round(b["bwd_mrays_accumulate"], 3),
+                                  "ms_minibatch_fwd_bwd_packed": round(b["ms_train_step_packed"], 4),
+                                  "bwd_mrays_packed": round(b["bwd_mrays_packed"], 3),
+                                  "ms_minibatch_fwd_bwd_packed_accumulate": round(b["ms_train_step_packed_accumulate"], 4),
+                                  "bwd_mrays_packed_accumulate": round(b["bwd_mrays_packed_accumulate"], 3),
                                   "ms_minibatch_fwd_bwd_patches": round(b["ms_train_step_patches"], 4),
                                   "bwd_mrays_patches": round(b["bwd_mrays_patches"], 3),
                                   "counters": b["counters"]}

@@ -94,7 +94,7 @@ int check_opts(const snerg_opts* o) {
     if (!std::isfinite(o->t_stop) || o->t_stop < 0.0f) return fail(SNERG_ERR_INVALID_ARG, "opts->t_stop must be finite and >= 0");
     const uint32_t known = SNERG_FLAG_MLP_FP16 | SNERG_FLAG_PERSISTENT | SNERG_FLAG_GRAPH | SNERG_FLAG_MLP_GRAD_ONLY |
                            SNERG_FLAG_NN_GATE | SNERG_FLAG_UNPREMULTIPLY | SNERG_FLAG_PER_SAMPLE_MLP |
-                           SNERG_FLAG_PATCH_RAYS | SNERG_FLAG_ACCUMULATE;
+                           SNERG_FLAG_PATCH_RAYS | SNERG_FLAG_ACCUMULATE | SNERG_FLAG_GRAD_PACKED;
     if (o->flags & ~known) return fail(SNERG_ERR_UNSUPPORTED, "unknown opts->flags bits");
     return SNERG_OK;
 }
@@ -722,7 +722,10 @@ int snerg_render_backward(snerg_handle* h, const snerg_grid* grid, const float* 
         return fail(SNERG_ERR_UNSUPPORTED, "grid gradients need a SNERG_F32 grid");
     if (!aux || !grad_rgba) return fail(SNERG_ERR_INVALID_ARG, "aux/grad_rgba is NULL");
     if (!grad_mlp) return fail(SNERG_ERR_INVALID_ARG, "grad_mlp is NULL");
-    if (!mlp_only && (!grad_dens || !grad_rgb || !grad_feat))
+    const bool packed = (opts->flags & SNERG_FLAG_GRAD_PACKED) != 0;
+    if (!mlp_only && packed && (!grad_dens || grad_rgb || grad_feat))
+        return fail(SNERG_ERR_INVALID_ARG, "SNERG_FLAG_GRAD_PACKED takes grad_dens only (grad_rgb, grad_feat NULL)");
+    if (!mlp_only && !packed && (!grad_dens || !grad_rgb || !grad_feat))
         return fail(SNERG_ERR_INVALID_ARG, "a grid gradient output is NULL");
     if (!h) return fail(SNERG_ERR_INVALID_ARG, "handle is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -743,9 +746,13 @@ int snerg_render_backward(snerg_handle* h, const snerg_grid* grid, const float* 
     if (rc) return rc;
     const bool accumulate = (opts->flags & SNERG_FLAG_ACCUMULATE) != 0;
     if (!mlp_only && !accumulate) {
-        HIP_TRY(launch_fill_f32(grad_dens, nv, 0.0f, s));
-        HIP_TRY(launch_fill_f32(grad_rgb, nv * 3, 0.0f, s));
-        HIP_TRY(launch_fill_f32(grad_feat, nv * 4, 0.0f, s));
+        if (packed) {
+            HIP_TRY(launch_fill_f32(grad_dens, nv * 8, 0.0f, s));
+        } else {
+            HIP_TRY(launch_fill_f32(grad_dens, nv, 0.0f, s));
+            HIP_TRY(launch_fill_f32(grad_rgb, nv * 3, 0.0f, s));
+            HIP_TRY(launch_fill_f32(grad_feat, nv * 4, 0.0f, s));
+        }
     }
     if (!accumulate) HIP_TRY(launch_fill_f32(grad_mlp, kMlpParams, 0.0f, s));
     if (n_rays == 0) return SNERG_OK;
@@ -771,6 +778,7 @@ int snerg_render_backward(snerg_handle* h, const snerg_grid* grid, const float* 
     a.tile_h = h->tuning.tile_h;
     a.mlp_only = mlp_only ? 1 : 0;
     a.patch_rays = (opts->flags & SNERG_FLAG_PATCH_RAYS) ? 1 : 0;
+    a.grad_packed = packed ? 1 : 0;
     if (ray_ids && !mlp_only && n_rays <= kBackwardListMaxRays && backward_aggregates(a.grid)) {
         rc = ensure_buffer(&h->d_list, &h->list_cap, size_t(n_rays) * kBackwardListCap * 4, s);
         if (rc) return rc;

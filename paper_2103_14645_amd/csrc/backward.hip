@@ -420,6 +420,11 @@ __device__ __forceinline__ void agg_scale(AggTable& t, float m) {
 }
 
 __device__ __forceinline__ void add_global(const BackwardArgs& a, int64_t vi, const float v[8], bool feat) {
+    if (a.grad_packed) {
+        float* g = a.grad_dens + 8 * vi;
+        for (int c = 0; c < (feat ? 8 : 4); ++c) unsafeAtomicAdd(g + c, v[c]);
+        return;
+    }
     unsafeAtomicAdd(a.grad_dens + vi, v[0]);
     unsafeAtomicAdd(a.grad_rgb + 3 * vi + 0, v[1]);
     unsafeAtomicAdd(a.grad_rgb + 3 * vi + 1, v[2]);
@@ -459,6 +464,7 @@ __device__ __forceinline__ bool agg_add(const AggTable& t, int32_t key, const fl
 // The device address of channel c (0 density, 1..3 RGB, 4..7 features) of
 // voxel key.
 __device__ __forceinline__ float* grad_channel(const BackwardArgs& a, int32_t key, int c) {
+    if (a.grad_packed) return a.grad_dens + 8 * int64_t(key) + c;
     return c == 0 ? a.grad_dens + key
                   : (c < 4 ? a.grad_rgb + 3 * int64_t(key) + (c - 1) : a.grad_feat + 4 * int64_t(key) + (c - 4));
 }

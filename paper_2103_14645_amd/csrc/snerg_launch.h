@@ -59,6 +59,7 @@ struct BackwardArgs {
     int32_t tile_w, tile_h;
     int32_t mlp_only;      // MLP gradient only: no re-march
     int32_t patch_rays;    // ray list in groups of 64 neighbouring rays
+    int32_t grad_packed;   // grid gradients as grad_dens[voxel][8] (grad_rgb, grad_feat unused)
     // short ray lists, two phases (null: one re-march): per list entry
     // kBackwardListCap listed samples, the count and the last listed k
     int4* list;

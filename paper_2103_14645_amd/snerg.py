@@ -42,6 +42,7 @@ SNERG_FLAG_UNPREMULTIPLY = 1 << 5
 SNERG_FLAG_PER_SAMPLE_MLP = 1 << 6
 SNERG_FLAG_PATCH_RAYS = 1 << 7
 SNERG_FLAG_ACCUMULATE = 1 << 8
+SNERG_FLAG_GRAD_PACKED = 1 << 9
 
 SNERG_MLP_PARAMS = 883
 
@@ -177,7 +178,7 @@ def make_cameras(cams):
 
 def make_opts(bg=(1.0, 1.0, 1.0), t_stop=1e-3, early_stop=True, mlp_on=True, fp16=False,
               persistent=False, graph=False, mlp_grad_only=False, nn_gate=False, unpremultiply=False,
-              per_sample_mlp=False, patch_rays=False, accumulate=False):
+              per_sample_mlp=False, patch_rays=False, accumulate=False, grad_packed=False):
     o = snerg_opts()
     o.bg[:] = [float(v) for v in bg]
     o.t_stop = float(t_stop)
@@ -187,7 +188,7 @@ def make_opts(bg=(1.0, 1.0, 1.0), t_stop=1e-3, early_stop=True, mlp_on=True, fp1
                | (SNERG_FLAG_GRAPH if graph else 0) | (SNERG_FLAG_MLP_GRAD_ONLY if mlp_grad_only else 0)
                | (SNERG_FLAG_NN_GATE if nn_gate else 0) | (SNERG_FLAG_UNPREMULTIPLY if unpremultiply else 0)
                | (SNERG_FLAG_PER_SAMPLE_MLP if per_sample_mlp else 0) | (SNERG_FLAG_PATCH_RAYS if patch_rays else 0)
-               | (SNERG_FLAG_ACCUMULATE if accumulate else 0))
+               | (SNERG_FLAG_ACCUMULATE if accumulate else 0) | (SNERG_FLAG_GRAD_PACKED if grad_packed else 0))
     return o
 
 

@@ -103,7 +103,7 @@ def test_render_validation_paths():
     assert call_render(mlp=None, opts=S.make_opts(mlp_on=False)) == S.SNERG_ERR_INVALID_ARG  # handle again
     assert "handle" in last_error()
     assert call_render(out=None) == S.SNERG_ERR_INVALID_ARG
-    o = S.make_opts(); o.flags = 1 << 9
+    o = S.make_opts(); o.flags = 1 << 10
     assert call_render(opts=o) == S.SNERG_ERR_UNSUPPORTED
     o = S.make_opts(); o.t_stop = float("inf")
     assert call_render(opts=o) == S.SNERG_ERR_INVALID_ARG
@@ -139,6 +139,13 @@ def test_backward_trace_pack_autotune_validation():
     assert bw(f32, gm=None) == S.SNERG_ERR_INVALID_ARG
     assert bw(f32) == S.SNERG_ERR_INVALID_ARG and "handle" in last_error()
     assert bw(f32, o=S.make_opts(fp16=True)) == S.SNERG_ERR_INVALID_ARG and "handle" in last_error()
+    # packed grid gradients: grad_dens only
+    assert bw(f32, o=S.make_opts(grad_packed=True)) == S.SNERG_ERR_INVALID_ARG and "GRAD_PACKED" in last_error()
+    bwp = lambda gr, gf: lib.snerg_render_backward(None, ctypes.byref(f32), FAKE, cams, 1, None, 32,
+                                                   ctypes.byref(S.make_opts(grad_packed=True)), FAKE, FAKE, FAKE,
+                                                   FAKE, gr, gf, None)
+    assert bwp(FAKE, None) == S.SNERG_ERR_INVALID_ARG and "GRAD_PACKED" in last_error()
+    assert bwp(None, None) == S.SNERG_ERR_INVALID_ARG and "handle" in last_error()
     tr = lambda mv, vis: lib.snerg_trace_visits(None, ctypes.byref(u8), cams, 1, None, 32, ctypes.byref(opts),
                                                 mv, vis, FAKE, None, None)
     assert tr(-1, FAKE) == S.SNERG_ERR_INVALID_ARG

@@ -398,3 +398,66 @@ def test_accumulate_flag_adds_minibatch_gradients(patch):
     for name, a_, b_, o_ in zip(("mlp", "dens", "rgb", "feat"), outs[True], outs[False], ref):
         compare(name + " accumulated vs summed", a_, b_)
         compare(name + " accumulated vs oracle", a_, o_)
+
+
+@pytest.mark.parametrize("layout,patch,mlp_on", [("views", False, True), ("scattered", False, True),
+                                                 ("patches", True, True), ("scattered", False, False)])
+def test_packed_grid_gradients(layout, patch, mlp_on):
+    # SNERG_FLAG_GRAD_PACKED: the grid gradients as one [voxel][8] array
+    # (density, RGB, features 0..3) hold the oracle's gradient as the three
+    # separate arrays do; a second, accumulating call over the same rays
+    # doubles them.  Whole views (summing table), scattered lists (log),
+    # patch lists (table), and no view network (four channels handed over).
+    say(f"packed grid gradients: {layout}, SNERG_FLAG_PATCH_RAYS={patch}, mlp_on={mlp_on}")
+    seed = 10
+    g = W.tiny_grid(n_occupied=180, seed=seed)
+    vals = shadow_values(g, seed)
+    mlp = W.mlp_weights(seed + 1)
+    cams = [W.orbit_camera(48, 40, seed=seed + 2), W.orbit_camera(24, 32, seed=seed + 3)]
+    n = sum(c.n_rays for c in cams)
+    rng = np.random.default_rng(seed)
+    og = O.OracleGrid(g, values=vals)
+    if layout == "views":
+        ids = None
+        alt = [O.render(og, mlp, cams, mlp_on=mlp_on, t_stop=1e-3 * f)["counters"] for f in (1 - 1e-5, 1 + 1e-5)]
+        assert np.array_equal(alt[0], alt[1])
+        m = n
+    else:
+        if layout == "patches":
+            class _C:
+                cam_list, mlp = cams, torch.zeros(1)
+            gen = torch.Generator()
+            gen.manual_seed(seed)
+            ids = F.MlpFineTuner.patch_order(_C(), gen).numpy()[: n // 2]
+        else:
+            ids = rng.permutation(n)[: n // 2]
+        ids = stable_ids(og, mlp, cams, ids)
+        m = len(ids)
+    g_rgba = rng.normal(size=(m, 4)) / m
+    h = handle()
+    r = A.ShadowRenderer(h, g.N, g.B, g.indirection, g.n_blocks)
+    dens, rgb, feat = (torch.from_numpy(v).cuda() for v in vals)
+    r.pack(dens, rgb, feat)
+    mt = S.mlp_tensor(mlp)
+    carr = S.make_cameras(cams)
+    idt = torch.from_numpy(ids.astype(np.int64)).cuda() if ids is not None else None
+    opts = S.make_opts(patch_rays=patch, mlp_on=mlp_on, grad_packed=True)
+    out = torch.empty((m, 4), device="cuda")
+    aux = torch.empty((m, 8), device="cuda")
+    S.snerg_render(h, r.struct(), mt, carr, idt, m, opts, out, aux)
+    gout = torch.from_numpy(g_rgba.astype(np.float32)).cuda()
+    nv = dens.numel()
+    gm = torch.empty(883, device="cuda")
+    gp = torch.full((nv, 8), float("nan"), device="cuda")  # overwritten (cleared) by the call
+    S.snerg_render_backward(h, r.struct(), mt, carr, idt, m, opts, aux, gout, gm, gp, None, None)
+    torch.cuda.synchronize()
+    once = gp.cpu().numpy().astype(np.float64)
+    om, od, orr, of = O.render_grad(og, mlp, cams, g_rgba, ray_ids=ids, mlp_on=mlp_on)
+    compare("mlp", gm.cpu().numpy().astype(np.float64), om)
+    compare("dens", once[:, 0], od.reshape(-1))
+    compare("rgb", once[:, 1:4], orr.reshape(-1, 3))
+    compare("feat", once[:, 4:], of.reshape(-1, 4))
+    acc = S.make_opts(patch_rays=patch, mlp_on=mlp_on, grad_packed=True, accumulate=True)
+    S.snerg_render_backward(h, r.struct(), mt, carr, idt, m, acc, aux, gout, gm, gp, None, None)
+    torch.cuda.synchronize()
+    compare("accumulated twice", gp.cpu().numpy().astype(np.float64), 2 * once)
