@@ -70,7 +70,8 @@ SOURCE_GROUPS = {"render": ("render.hip", "render_ps.hip", "march.h", "mlp.h", "
 LEG_GROUP = {"plain512": "render", "batched1024": "render", "large1024": "render", "adjoint512_fwd": "render",
              "nondeferred_fp32": "render", "nondeferred_fp16": "render", "large1024_mb_fwd": "render",
              "adjoint512_bwd": "backward", "adjoint512_mlp_bwd": "backward", "large1024_mb_mlp_bwd": "backward",
-             "large1024_mb_bwd": "backward", "large1024_mb_bwd_patch": "backward", "large1024_mb_record": "backward"}
+             "large1024_mb_bwd": "backward", "large1024_mb_bwd_patch": "backward", "large1024_mb_record": "backward",
+             "large1024_mb_bwd_packed": "backward"}
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "counters_by_kernel.md")
 COPY_BYTES = 1 << 30
 TIMING_EVERY = 4  # frames per kernel-timed frame in the plain leg's timed region
