@@ -462,9 +462,8 @@ __device__ __forceinline__ bool agg_add(const AggTable& t, int32_t key, const fl
 }
 
 // The device address of channel c (0 density, 1..3 RGB, 4..7 features) of
-// voxel key.
+// voxel key in the three separate gradient arrays.
 __device__ __forceinline__ float* grad_channel(const BackwardArgs& a, int32_t key, int c) {
-    if (a.grad_packed) return a.grad_dens + 8 * int64_t(key) + c;
     return c == 0 ? a.grad_dens + key
                   : (c < 4 ? a.grad_rgb + 3 * int64_t(key) + (c - 1) : a.grad_feat + 4 * int64_t(key) + (c - 4));
 }
@@ -476,6 +475,17 @@ template <bool FEAT>
 __device__ __forceinline__ void log_flush(const BackwardArgs& a, const AggTable& t, int lane, int n) {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
+    if (a.grad_packed) {
+        constexpr int kC = FEAT ? 8 : 4;  // lanes per entry, one channel each
+        const int c = lane % kC;
+        for (int e = lane / kC; e < n; e += 64 / kC) {
+            const float v = t.val[c * kAggSlots + e];
+            if (v != 0.0f) unsafeAtomicAdd(a.grad_dens + 8 * int64_t(t.key[e]) + c, v);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        return;
+    }
     const int c = lane & 3;
     for (int e = lane >> 2; e < n; e += 16) {
         const int32_t key = t.key[e];
@@ -497,29 +507,50 @@ __device__ __forceinline__ void log_flush(const BackwardArgs& a, const AggTable&
 // the entries: lane l takes entry l / 4 of a group of 16 and within it
 // channels l % 4 and l % 4 + 4, so that one instruction adds an entry's
 // density and colour (two lines) and the next its four features (one
-// line), where one lane per entry would touch seven lines.
+// line), where one lane per entry would touch seven lines.  With packed
+// gradients an entry's eight sums share one line: eight lanes per entry (four
+// without features), one instruction per group.
 template <bool FEAT>
 __device__ __forceinline__ void agg_flush(const BackwardArgs& a, const AggTable& t, int lane) {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    const int c = lane & 3;
     int32_t* iv = reinterpret_cast<int32_t*>(t.val);
-    for (int sl = lane >> 2; sl < kAggSlots; sl += 16) {
-        const int32_t key = t.key[sl];
-        if (key >= 0) {
-            float v0;
-            if (c == 0) {
-                v0 = t.val[sl];
-                t.val[sl] = 0.0f;
-            } else {
-                v0 = float(iv[c * kAggSlots + sl]) * t.dq;
-                iv[c * kAggSlots + sl] = 0;
+    if (a.grad_packed) {
+        constexpr int kC = FEAT ? 8 : 4;
+        const int c = lane % kC;
+        for (int sl = lane / kC; sl < kAggSlots; sl += 64 / kC) {
+            const int32_t key = t.key[sl];
+            if (key >= 0) {
+                float v;
+                if (c == 0) {
+                    v = t.val[sl];
+                    t.val[sl] = 0.0f;
+                } else {
+                    v = float(iv[c * kAggSlots + sl]) * t.dq;
+                    iv[c * kAggSlots + sl] = 0;
+                }
+                if (v != 0.0f) unsafeAtomicAdd(a.grad_dens + 8 * int64_t(key) + c, v);
             }
-            if (v0 != 0.0f) unsafeAtomicAdd(grad_channel(a, key, c), v0);
-            if (FEAT) {
-                const float v1 = float(iv[(c + 4) * kAggSlots + sl]) * t.dq;
-                iv[(c + 4) * kAggSlots + sl] = 0;
-                if (v1 != 0.0f) unsafeAtomicAdd(grad_channel(a, key, c + 4), v1);
+        }
+    } else {
+        const int c = lane & 3;
+        for (int sl = lane >> 2; sl < kAggSlots; sl += 16) {
+            const int32_t key = t.key[sl];
+            if (key >= 0) {
+                float v0;
+                if (c == 0) {
+                    v0 = t.val[sl];
+                    t.val[sl] = 0.0f;
+                } else {
+                    v0 = float(iv[c * kAggSlots + sl]) * t.dq;
+                    iv[c * kAggSlots + sl] = 0;
+                }
+                if (v0 != 0.0f) unsafeAtomicAdd(grad_channel(a, key, c), v0);
+                if (FEAT) {
+                    const float v1 = float(iv[(c + 4) * kAggSlots + sl]) * t.dq;
+                    iv[(c + 4) * kAggSlots + sl] = 0;
+                    if (v1 != 0.0f) unsafeAtomicAdd(grad_channel(a, key, c + 4), v1);
+                }
             }
         }
     }
