@@ -129,7 +129,7 @@ extern "C" {
  * the three separate arrays, up to float summation order.  gfx950 serves
  * device float atomics per 64-byte cache line, and a voxel's eight sums then
  * share one line instead of three, which speeds up ray lists whose rays
- * share few voxels (about 1.2x on scattered minibatches). */
+ * share few voxels (1.2x to 1.6x on scattered minibatches). */
 #define SNERG_FLAG_GRAD_PACKED (1u << 9)
 
 #define SNERG_MLP_PARAMS 883 /* W1[16][34] b1[16] W2[16][16] b2[16] W3[3][16] b3[3], [out][in] */
