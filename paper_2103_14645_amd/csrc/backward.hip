@@ -336,7 +336,7 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_backward(BackwardArgs a)
 // coordinates b.  Voxels outside the grid or in empty blocks are structural
 // zeros and have no slot (-1).
 __device__ __forceinline__ int64_t canonical_voxel(const GridArgs& g, int32_t id, const int32_t b[3],
-                                                   int vx, int vy, int vz) {
+                                                   int vx, int vy, int vz, int32_t& nb_lin, int32_t& nb_id) {
     const int B = g.B;
     int32_t tid = id;
     if (tid < 0 || tid >= g.n_blocks) return -1;
@@ -345,7 +345,13 @@ __device__ __forceinline__ int64_t canonical_voxel(const GridArgs& g, int32_t id
         const int ny = b[1] + (vy < 0 ? -1 : (vy >= B ? 1 : 0));
         const int nz = b[2] + (vz < 0 ? -1 : (vz >= B ? 1 : 0));
         if (nx < 0 || ny < 0 || nz < 0 || nx >= g.G || ny >= g.G || nz >= g.G) return -1;
-        tid = g.ind[(nz * g.G + ny) * g.G + nx];
+        // the last neighbour looked up (a ray runs along a face for a while)
+        const int32_t nlin = (nz * g.G + ny) * g.G + nx;
+        if (nlin != nb_lin) {
+            nb_lin = nlin;
+            nb_id = g.ind[nlin];
+        }
+        tid = nb_id;
         if (tid < 0 || tid >= g.n_blocks) return -1;
         vx &= B - 1;
         vy &= B - 1;
@@ -569,12 +575,13 @@ __device__ __forceinline__ int wave_sum_i32(int v) {
 
 template <bool FEAT, bool AGG>
 __device__ __forceinline__ void flush_corner(const BackwardArgs& a, const AggTable& t, const CellWindow& w, int c,
-                                             const float gC[3], const float gV[4], int& fresh) {
+                                             const float gC[3], const float gV[4], int& fresh, int32_t& nb_lin,
+                                             int32_t& nb_id) {
     const float A = w.A[c], D = w.D[c];
     if (A == 0.0f && D == 0.0f) return;
     const GridArgs& g = a.grid;
     const int64_t vi = canonical_voxel(g, w.id, w.b, w.c[0] + (c & 1) - 1, w.c[1] + ((c >> 1) & 1) - 1,
-                                       w.c[2] + (c >> 2) - 1);
+                                       w.c[2] + (c >> 2) - 1, nb_lin, nb_id);
     if (vi < 0) return;
     float v[8] = {g.sigma_scale * D, A * gC[0], A * gC[1], A * gC[2], 0.f, 0.f, 0.f, 0.f};
     if (FEAT) {
@@ -598,6 +605,7 @@ struct AdjointRay {
     bool early, nn_gate;
     CellWindow win;
     int fresh;  // this lane's new table keys since the last count
+    int32_t nb_lin, nb_id;  // the last neighbouring block looked up: linear index, atlas id
     // LOG: the corners handed over since the last commit, by corner index
     uint32_t pmask;
     int32_t pvi[8];
@@ -643,6 +651,8 @@ struct AdjointRay {
         for (int c = 0; c < 8; ++c) win.A[c] = win.D[c] = 0.0f;
         fresh = 0;
         pmask = 0;
+        nb_lin = -1;
+        nb_id = -1;
         return live;
     }
 
@@ -651,7 +661,7 @@ struct AdjointRay {
         const float A = win.A[c], D = win.D[c];
         if (A == 0.0f && D == 0.0f) return;
         const int64_t vi = canonical_voxel(g, win.id, win.b, win.c[0] + (c & 1) - 1, win.c[1] + ((c >> 1) & 1) - 1,
-                                           win.c[2] + (c >> 2) - 1);
+                                           win.c[2] + (c >> 2) - 1, nb_lin, nb_id);
         if (vi < 0) return;
         pvi[c] = int32_t(vi);  // LOG runs only on grids of fewer than 2^31 voxels
         pA[c] = A;
@@ -748,7 +758,7 @@ struct AdjointRay {
         for (int c = 0; c < 8; ++c)
             if ((leave >> c) & 1u) {
                 if (LOG) stash(g, c);
-                else flush_corner<FEAT, AGG>(a, tab, win, c, gC, gV, fresh);
+                else flush_corner<FEAT, AGG>(a, tab, win, c, gC, gV, fresh, nb_lin, nb_id);
             }
         if (jump) {
 #pragma unroll
@@ -792,7 +802,7 @@ struct AdjointRay {
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
                 if (LOG) stash(a.grid, c);
-                else flush_corner<FEAT, AGG>(a, tab, win, c, gC, gV, fresh);
+                else flush_corner<FEAT, AGG>(a, tab, win, c, gC, gV, fresh, nb_lin, nb_id);
             }
         }
     }
