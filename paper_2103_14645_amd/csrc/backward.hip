@@ -960,8 +960,9 @@ __global__ __launch_bounds__(64 * kAggWaves) void k_backward_from_list(BackwardA
     const int wave = threadIdx.x >> 6;
     AggTable tab = agg_table(s_occ, g.n_words, wave, lane, true);
     __syncthreads();
-    const int64_t i = (int64_t(blockIdx.x) * kAggWaves + wave) * 64 + lane;
-    bool live = i < a.n_rays;
+    // a.list_rpw rays per wavefront (lanes past them idle)
+    const int64_t i = (int64_t(blockIdx.x) * kAggWaves + wave) * a.list_rpw + lane;
+    bool live = lane < a.list_rpw && i < a.n_rays;
     AdjointRay<FEAT, true, LOG> st;
     live = st.setup(a, i, live);
     if (!LOG) st.table_scale(tab);
@@ -1085,23 +1086,30 @@ hipError_t launch_backward(const BackwardArgs& a, int n_groups, hipStream_t s) {
     const bool feat = a.mlp_mode != kMlpOff;
     (void)n_vox;
     if (a.list) {  // short ray list: record, then the gradient from the lists
+        // A scattered list of up to 2^16 rays fills at most one wavefront
+        // per SIMD at 64 rays each, and a lone wavefront waits on its own
+        // latencies: with 32 rays (lanes 32..63 idle) two share each SIMD.
+        // Patch lists keep 64, the 8x8 patches whose voxels the table sums.
+        BackwardArgs b = a;
+        b.list_rpw = (!a.patch_rays && a.n_rays <= (int64_t(1) << 16)) ? 32 : 64;
+        const unsigned lblocks = unsigned(((a.n_rays + b.list_rpw - 1) / b.list_rpw + kAggWaves - 1) / kAggWaves);
         const size_t occ = size_t(a.grid.n_words) * sizeof(uint2);
         hipLaunchKernelGGL(k_backward_record, dim3(unsigned((a.n_rays + 255) / 256)), dim3(256), occ, s, a, a.list,
                            a.list_count, a.list_klast);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         // scattered rays share few voxels: the log; patches: the aggregating table
         if (feat && a.patch_rays)
-            hipLaunchKernelGGL((k_backward_from_list<true, false>), dim3(blocks), dim3(64 * kAggWaves), lds, s, a,
-                               a.list, a.list_count, a.list_klast);
+            hipLaunchKernelGGL((k_backward_from_list<true, false>), dim3(lblocks), dim3(64 * kAggWaves), lds, s, b,
+                               b.list, b.list_count, b.list_klast);
         else if (feat)
-            hipLaunchKernelGGL((k_backward_from_list<true, true>), dim3(blocks), dim3(64 * kAggWaves), lds, s, a,
-                               a.list, a.list_count, a.list_klast);
+            hipLaunchKernelGGL((k_backward_from_list<true, true>), dim3(lblocks), dim3(64 * kAggWaves), lds, s, b,
+                               b.list, b.list_count, b.list_klast);
         else if (a.patch_rays)
-            hipLaunchKernelGGL((k_backward_from_list<false, false>), dim3(blocks), dim3(64 * kAggWaves), lds, s, a,
-                               a.list, a.list_count, a.list_klast);
+            hipLaunchKernelGGL((k_backward_from_list<false, false>), dim3(lblocks), dim3(64 * kAggWaves), lds, s, b,
+                               b.list, b.list_count, b.list_klast);
         else
-            hipLaunchKernelGGL((k_backward_from_list<false, true>), dim3(blocks), dim3(64 * kAggWaves), lds, s, a,
-                               a.list, a.list_count, a.list_klast);
+            hipLaunchKernelGGL((k_backward_from_list<false, true>), dim3(lblocks), dim3(64 * kAggWaves), lds, s, b,
+                               b.list, b.list_count, b.list_klast);
         return hipGetLastError();
     }
     if (feat && agg)

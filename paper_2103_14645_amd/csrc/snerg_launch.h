@@ -60,6 +60,7 @@ struct BackwardArgs {
     int32_t mlp_only;      // MLP gradient only: no re-march
     int32_t patch_rays;    // ray list in groups of 64 neighbouring rays
     int32_t grad_packed;   // grid gradients as grad_dens[voxel][8] (grad_rgb, grad_feat unused)
+    int32_t list_rpw;      // set by the launch: rays per wavefront of the list gradient pass
     // short ray lists, two phases (null: one re-march): per list entry
     // kBackwardListCap listed samples, the count and the last listed k
     int4* list;

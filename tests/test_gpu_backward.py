@@ -461,3 +461,26 @@ def test_packed_grid_gradients(layout, patch, mlp_on):
     S.snerg_render_backward(h, r.struct(), mt, carr, idt, m, acc, aux, gout, gm, gp, None, None)
     torch.cuda.synchronize()
     compare("accumulated twice", gp.cpu().numpy().astype(np.float64), 2 * once)
+
+
+@pytest.mark.parametrize("n_list", [65536, 65537 + 4000])
+def test_scattered_lists_either_side_of_the_wavefront_split(n_list):
+    # Scattered lists of up to 2^16 rays run the list gradient pass with 32
+    # rays per wavefront, longer ones with 64: both against the oracle.
+    say(f"scattered list of {n_list} rays")
+    seed = 16
+    g = W.tiny_grid(n_occupied=120, seed=seed)
+    vals = shadow_values(g, seed)
+    mlp = W.mlp_weights(seed + 1)
+    cams = [W.orbit_camera(320, 240, seed=seed + 2)]
+    og = O.OracleGrid(g, values=vals)
+    rng = np.random.default_rng(seed)
+    ids = stable_ids(og, mlp, cams, rng.permutation(cams[0].n_rays)[:n_list + 64])[:n_list]
+    assert len(ids) == n_list
+    g_rgba = rng.normal(size=(n_list, 4)) / n_list
+    gm, gd, gr, gf, _ = run_backward(g, vals, mlp, cams, g_rgba, ids=ids)
+    om, od, orr, of = O.render_grad(og, mlp, cams, g_rgba, ray_ids=ids)
+    compare("mlp", gm, om)
+    compare("dens", gd, od)
+    compare("rgb", gr, orr)
+    compare("feat", gf, of)
