@@ -1088,10 +1088,11 @@ hipError_t launch_backward(const BackwardArgs& a, int n_groups, hipStream_t s) {
     if (a.list) {  // short ray list: record, then the gradient from the lists
         // A scattered list of up to 2^16 rays fills at most one wavefront
         // per SIMD at 64 rays each, and a lone wavefront waits on its own
-        // latencies: with 32 rays (lanes 32..63 idle) two share each SIMD.
-        // Patch lists keep 64, the 8x8 patches whose voxels the table sums.
+        // latencies: with 32 rays (up to 2^16) or 16 (up to 2^15), the other
+        // lanes idle, two or more share each SIMD.  Patch lists keep 64, the
+        // 8x8 patches whose voxels the table sums.
         BackwardArgs b = a;
-        b.list_rpw = (!a.patch_rays && a.n_rays <= (int64_t(1) << 16)) ? 32 : 64;
+        b.list_rpw = a.patch_rays ? 64 : (a.n_rays <= (int64_t(1) << 15) ? 16 : (a.n_rays <= (int64_t(1) << 16) ? 32 : 64));
         const unsigned lblocks = unsigned(((a.n_rays + b.list_rpw - 1) / b.list_rpw + kAggWaves - 1) / kAggWaves);
         const size_t occ = size_t(a.grid.n_words) * sizeof(uint2);
         hipLaunchKernelGGL(k_backward_record, dim3(unsigned((a.n_rays + 255) / 256)), dim3(256), occ, s, a, a.list,

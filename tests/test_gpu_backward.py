@@ -463,10 +463,10 @@ def test_packed_grid_gradients(layout, patch, mlp_on):
     compare("accumulated twice", gp.cpu().numpy().astype(np.float64), 2 * once)
 
 
-@pytest.mark.parametrize("n_list", [65536, 65537 + 4000])
+@pytest.mark.parametrize("n_list", [32768, 65536, 65537 + 4000])
 def test_scattered_lists_either_side_of_the_wavefront_split(n_list):
-    # Scattered lists of up to 2^16 rays run the list gradient pass with 32
-    # rays per wavefront, longer ones with 64: both against the oracle.
+    # Scattered lists run the list gradient pass with 16 rays per wavefront
+    # up to 2^15 rays, 32 up to 2^16 and 64 above: each against the oracle.
     say(f"scattered list of {n_list} rays")
     seed = 16
     g = W.tiny_grid(n_occupied=120, seed=seed)
