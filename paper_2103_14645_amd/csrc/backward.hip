@@ -922,8 +922,10 @@ __global__ __launch_bounds__(256) void k_backward_record(BackwardArgs a, int4* _
     const GridArgs& g = a.grid;
     for (int w = threadIdx.x; w < g.n_words; w += blockDim.x) s_occ[w] = g.occ[w];
     __syncthreads();
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= a.n_rays) return;
+    // a.list_rpw rays per wavefront, as in the gradient pass
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)) * a.list_rpw + lane;
+    if (lane >= a.list_rpw || i >= a.n_rays) return;
     int32_t n = 0;
     int64_t kl = 0;
     // rays that composited nothing have no grid gradient (phase 2 skips them)
@@ -1095,8 +1097,9 @@ hipError_t launch_backward(const BackwardArgs& a, int n_groups, hipStream_t s) {
         b.list_rpw = a.patch_rays ? 64 : (a.n_rays <= (int64_t(1) << 15) ? 16 : (a.n_rays <= (int64_t(1) << 16) ? 32 : 64));
         const unsigned lblocks = unsigned(((a.n_rays + b.list_rpw - 1) / b.list_rpw + kAggWaves - 1) / kAggWaves);
         const size_t occ = size_t(a.grid.n_words) * sizeof(uint2);
-        hipLaunchKernelGGL(k_backward_record, dim3(unsigned((a.n_rays + 255) / 256)), dim3(256), occ, s, a, a.list,
-                           a.list_count, a.list_klast);
+        const unsigned rblocks = unsigned(((a.n_rays + b.list_rpw - 1) / b.list_rpw + 3) / 4);
+        hipLaunchKernelGGL(k_backward_record, dim3(rblocks), dim3(256), occ, s, b, b.list, b.list_count,
+                           b.list_klast);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         // scattered rays share few voxels: the log; patches: the aggregating table
         if (feat && a.patch_rays)
