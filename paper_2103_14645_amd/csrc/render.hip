@@ -189,7 +189,7 @@ __global__ __launch_bounds__(256) void k_render(RenderArgs a) {
     const int wpg = blockDim.x >> 6;
     // One inlined copy of the per-ray body; the launch modes differ only in
     // how a wavefront obtains its next 64 rays (wave-uniform control flow).
-    int64_t t = a.mode == kModeList ? int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63)
+    int64_t t = a.mode == kModeList ? (int64_t(blockIdx.x) * wpg + wave) * a.list_rpw
                                     : int64_t(xcd_grouped(blockIdx.x, gridDim.x)) * wpg + wave;
     for (;;) {
         if (PERSIST) {
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(256) void k_render(RenderArgs a) {
         if (a.mode == kModeList) {
             if (t >= a.n_rays) break;  // wave-uniform
             out_idx = t + lane;
-            valid = out_idx < a.n_rays;
+            valid = lane < a.list_rpw && out_idx < a.n_rays;
             if (valid) {
                 const int64_t r = a.ray_ids[out_idx];
                 ci = find_camera_by_ray(a.cams, a.n_cams, r);
@@ -374,10 +374,15 @@ hipError_t launch_tile_order(const RenderArgs& a, uint8_t* cls, int32_t* counts,
 }
 
 template <int VT, int MLP>
-static hipError_t launch_render_t(const RenderArgs& a, int wpg, int n_groups, hipStream_t s) {
+static hipError_t launch_render_t(const RenderArgs& args, int wpg, int n_groups, hipStream_t s) {
     const int threads = 64 * wpg;
+    // A ray list of up to 2^16 rays fills at most one wavefront per SIMD at
+    // 64 rays each, and a lone wavefront waits on its own latencies: such
+    // lists go 32 (up to 2^16) or 16 (up to 2^15) rays to a wavefront.
+    RenderArgs a = args;
+    a.list_rpw = a.n_rays <= (int64_t(1) << 15) ? 16 : (a.n_rays <= (int64_t(1) << 16) ? 32 : 64);
     unsigned blocks;
-    if (a.mode == kModeList) blocks = unsigned((a.n_rays + threads - 1) / threads);
+    if (a.mode == kModeList) blocks = unsigned(((a.n_rays + a.list_rpw - 1) / a.list_rpw + wpg - 1) / wpg);
     else if (a.mode == kModeTiles) blocks = unsigned((a.total_tiles + wpg - 1) / wpg);
     else blocks = unsigned(n_groups);
     if (blocks == 0) return hipSuccess;

@@ -28,6 +28,7 @@ struct RenderArgs {
     int64_t n_rays;
     int64_t total_tiles;
     int32_t tile_w, tile_h;  // tile_w * tile_h == 64
+    int32_t list_rpw;        // set by the launch: rays per wavefront of a ray-list launch
     int32_t* tile_counter;   // persistent mode
     const int32_t* tile_order;  // tile of each wavefront slot / queue entry (null: identity)
     float* out;              // [n][4]
