@@ -465,8 +465,9 @@ def test_packed_grid_gradients(layout, patch, mlp_on):
 
 @pytest.mark.parametrize("n_list", [32768, 65536, 65537 + 4000])
 def test_scattered_lists_either_side_of_the_wavefront_split(n_list):
-    # Scattered lists run the list gradient pass with 16 rays per wavefront
-    # up to 2^15 rays, 32 up to 2^16 and 64 above: each against the oracle.
+    # Scattered lists run the list gradient pass (and the ray-list render)
+    # with 16 rays per wavefront up to 2^15 rays, 32 up to 2^16 and 64
+    # above: gradients and the rendered colours against the oracle.
     say(f"scattered list of {n_list} rays")
     seed = 16
     g = W.tiny_grid(n_occupied=120, seed=seed)
@@ -478,9 +479,10 @@ def test_scattered_lists_either_side_of_the_wavefront_split(n_list):
     ids = stable_ids(og, mlp, cams, rng.permutation(cams[0].n_rays)[:n_list + 64])[:n_list]
     assert len(ids) == n_list
     g_rgba = rng.normal(size=(n_list, 4)) / n_list
-    gm, gd, gr, gf, _ = run_backward(g, vals, mlp, cams, g_rgba, ids=ids)
+    gm, gd, gr, gf, out = run_backward(g, vals, mlp, cams, g_rgba, ids=ids)
     om, od, orr, of = O.render_grad(og, mlp, cams, g_rgba, ray_ids=ids)
     compare("mlp", gm, om)
     compare("dens", gd, od)
     compare("rgb", gr, orr)
     compare("feat", gf, of)
+    assert np.abs(out - O.render(og, mlp, cams, ray_ids=ids)["rgba"]).max() <= 1e-4
